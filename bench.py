@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark: D-Iteration vs power iteration to a certified L1 distance of 1e-8 on the
+50M-node web-like graph (float fluid, double history and residual), one MI355X.
+
+One step = one D-Iteration solve from F_0 = (1-d) Z to |F|_1 / (1-d) <= 1e-8
+(di_reset + di_diffuse).  K power-iteration solves to the same certified tolerance
+are timed after the K steps.  Graph generation, upload and the device-side graph
+build happen before the timed region; inputs are resident in HBM when it starts.
+
+Prints one JSON line (rank 0).  See DESIGN.md for the byte model behind "roofline".
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+D = 0.85
+TOL = 1e-8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def di_algorithmic_bytes(s, n, st_sweeps, fp32):
+    """Bytes the block-local sweep must move (per-unit model)."""
+    from paper_1501_06350_amd import binding as B
+    T = 4 if fp32 else 8
+    m_rem = s.info(B.INFO_M_REMOTE)
+    nr = s.info(B.INFO_NRANGES)
+    local = s.info(B.INFO_LOCAL_PUSHES)
+    return {
+        # per sweep: F read + write, in-flight write, cross-range entries (src 4 + tgt 2 + gather T)
+        "per_sweep": n * 3 * T + m_rem * (6 + T) + nr * 16,
+        # per diffusion: H read+write 16, 1/s_j 8, remote weight 8, local row pointers 16
+        "per_diffusion": 48,
+        # per local push: 2-byte target index (the update itself stays in LDS)
+        "per_local_push": 2,
+        "local_pushes": local,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=50_000_000)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--fp64", action="store_true", help="double fluid instead of float")
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--range-log2", type=int, default=0)
+    ap.add_argument("--rounds", type=int, default=0)
+    ap.add_argument("--theta", type=float, default=1.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every box here has a single MI355X, and the multi-GPU "
+              "partitioning of the sweep is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1501_06350_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    fp32 = not args.fp64
+    t0 = time.time()
+    g = W.webgen(args.n, args.seed)
+    log("graph webgen(n=%d, seed=%d): m=%d generated in %.1fs" % (g.n, args.seed, g.m, time.time() - t0))
+    t0 = time.time()
+    s = B.from_graph(g, d=D, fluid_fp32=fp32, timing=True, range_log2=args.range_log2, inner_rounds=args.rounds,
+                     theta=args.theta)
+    log("di_init (upload + IN build + block-local split) %.1fs, device bytes %.2f GB" %
+        (time.time() - t0, s.info(B.INFO_DEVICE_BYTES) / 1e9))
+    n, m = g.n, g.m
+
+    def di_step():
+        s.reset()
+        return s.diffuse(TOL)
+
+    for _ in range(args.warmup):
+        st = di_step()
+        log("warmup DI: sweeps=%d ms=%.2f bound=%.3e" % (st["sweeps"], st["ms"], st["bound"]))
+    torch.cuda.synchronize()
+    stats = []
+    kern_ns, kern_launch = 0, 0
+    local_pushes = 0
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        st = di_step()
+        stats.append(st)
+        kern_ns += s.info(B.INFO_KERNEL_NS)
+        kern_launch += s.info(B.INFO_KERNEL_LAUNCHES)
+        local_pushes += s.info(B.INFO_LOCAL_PUSHES)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = 1e3 * wall / args.steps
+    edges = sum(x["edge_updates"] for x in stats) / args.steps
+    sweeps = sum(x["sweeps"] for x in stats) / args.steps
+    diffusions = sum(x["node_updates"] for x in stats) / args.steps
+    di_ms = sum(x["ms"] for x in stats) / args.steps
+    assert all(x["converged"] for x in stats)
+    geups = edges / (ms_per_step * 1e-3) / 1e9
+    log("DI: %.2f ms/step (device %.2f ms), sweeps %.1f, edge updates %.3e, rounds %.2f, GEUPS %.1f" %
+        (ms_per_step, di_ms, sweeps, edges, edges / m, geups))
+
+    # roofline of the dominant kernel (the block-local sweep)
+    T = 4 if fp32 else 8
+    m_rem = s.info(B.INFO_M_REMOTE)
+    nr = s.info(B.INFO_NRANGES)
+    per_sweep = n * 3 * T + m_rem * (6 + T) + nr * 16
+    alg_bytes = sweeps * args.steps * per_sweep + diffusions * args.steps * 48 + local_pushes * 2
+    avg_ns = kern_ns / max(kern_launch, 1)
+    bytes_per_launch = alg_bytes / max(kern_launch, 1)
+    achieved = bytes_per_launch / avg_ns  # GB/s (bytes per ns)
+    log("block-local sweep kernel: %d launches, avg %.1f us, %.3f GB/launch -> %.0f GB/s" %
+        (kern_launch, avg_ns / 1e3, bytes_per_launch / 1e9, achieved))
+
+    # power iteration to the same certified tolerance
+    pi = []
+    s.power(TOL)  # warm-up (allocates and builds row blocks)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pk_ns, pk_l = 0, 0
+    for _ in range(args.steps):
+        p = s.power(TOL)
+        pi.append(p)
+        pk_ns += s.info(B.INFO_KERNEL_NS)
+        pk_l += s.info(B.INFO_KERNEL_LAUNCHES)
+    torch.cuda.synchronize()
+    pi_ms = 1e3 * (time.perf_counter() - t1) / args.steps
+    pi_iters = pi[-1]["sweeps"]
+    pi_geups = pi_iters * m / (pi_ms * 1e-3) / 1e9
+    pi_bytes_iter = m * (4 + T) + n * (8 + 8 + 8 + T + 8)  # idx+gather per edge; ptr,x,x_new,xt,inv_s per node
+    pi_achieved = pi_bytes_iter / (pk_ns / max(pk_l, 1))
+    xd, xp = s.read(B.H), s.read(B.X_PI)
+    di_pi_l1 = float(np.abs(xd - xp).sum())
+    log("PI: %.2f ms/solve, %d iterations, GEUPS %.1f, kernel avg %.1f us -> %.0f GB/s; |x_DI - x_PI|_1 = %.2e" %
+        (pi_ms, pi_iters, pi_geups, pk_ns / max(pk_l, 1) / 1e3, pi_achieved, di_pi_l1))
+
+    result = {
+        "metric": "GEUPS + time-to-L1 1e-8, DI vs power iter, 50M nodes; k=64 batched PPR",
+        "value": round(geups, 3),
+        "unit": "GEUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if fp32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "webgen n=%d m=%d seed=%d, d=0.85, uniform Z, L1 tol 1e-8, %s fluid + f64 history" %
+                               (n, m, args.seed, "f32" if fp32 else "f64"),
+                   "range_log2": s.info(B.INFO_RANGE_LOG2), "inner_rounds": s.info(B.INFO_INNER_ROUNDS),
+                   "theta": args.theta},
+        "time_to_tol_ms": {"di": round(ms_per_step, 3), "pi": round(pi_ms, 3)},
+        "di_vs_pi_speedup": round(pi_ms / ms_per_step, 3),
+        "di": {"sweeps": sweeps, "edge_updates": edges, "diffusions": diffusions, "rounds": round(edges / m, 3),
+               "device_ms": round(di_ms, 3)},
+        "pi": {"iterations": pi_iters, "geups": round(pi_geups, 3),
+               "roofline": {"bound": "hbm", "achieved": round(pi_achieved, 1), "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(pi_achieved / HBM_PEAK_GBS, 4)}},
+        "di_pi_l1_diff": di_pi_l1,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_bld_sweep", "launches": kern_launch, "avg_us": round(avg_ns / 1e3, 2)},
+    }
+    s.close()
+    del xd, xp
+
+    if args.batched:
+        try:
+            result["batched"] = bench_batched(fp32)
+        except Exception as e:  # reported, not fatal: the headline is the single solve
+            result["batched"] = {"error": str(e)[:300]}
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(g, args.cpu_sweeps)
+    print(json.dumps(result), flush=True)
+
+
+def bench_batched(fp32):
+    """k=64 personalized PageRank on webgen(4M): one batched solve vs 64 single solves."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1501_06350_amd import binding as B
+    g = W.webgen(4_000_000, 4)
+    Z = W.ppr_Z(g.n, 64, 16, 4)
+    out = {}
+    # single solves need their own Z: one context per column (graph build excluded from timing)
+    singles = 0.0
+    for c in range(64):
+        with B.from_graph(g, d=D, Z=np.ascontiguousarray(Z[:, c]), fluid_fp32=True) as sc:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sc.diffuse(TOL)
+            torch.cuda.synchronize()
+            singles += time.perf_counter() - t
+    out["single_total_ms"] = round(1e3 * singles, 3)
+    try:
+        with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=True) as sb:
+            sb.diffuse(TOL)
+            sb.reset()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = sb.diffuse(TOL)
+            torch.cuda.synchronize()
+            out["batched_ms"] = round(1e3 * (time.perf_counter() - t), 3)
+            out["speedup"] = round(out["single_total_ms"] / out["batched_ms"], 3)
+            out["batched_sweeps"] = st["sweeps"]
+    except B.DIError as e:
+        out["batched_error"] = str(e)[:200]
+    return out
+
+
+def cpu_baseline(g, sweeps):
+    """The oracle's synchronous sweep on the same graph, a bounded number of sweeps."""
+    import oracle as O
+    t0 = time.time()
+    og = O.OGraph.of(g)
+    log("oracle graph build %.1fs" % (time.time() - t0))
+    y = O.SyncDI(og, D, O.uniform_Z(g.n), fluid_fp32=True)
+    t = time.perf_counter()
+    y.run(TOL, max_sweeps=sweeps)
+    dt = time.perf_counter() - t
+    edges = sum(tr[2] for tr in y.trace)
+    return {"value": round(edges / dt / 1e9, 5), "unit": "GEUPS", "cores": 1, "kind": "oracle",
+            "sample": "first %d synchronous sweeps of the oracle's D-Iteration (float fluid) on the same "
+                      "webgen graph, %.3e edge updates in %.1f s" % (sweeps, edges, dt)}
+
+
+if __name__ == "__main__":
+    main()

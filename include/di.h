@@ -1,0 +1,216 @@
+/*
+ * di.h - D-Iteration (fluid diffusion) and power iteration for PageRank on one
+ * AMD Instinct MI355X (gfx950).  C ABI: plain pointers and sizes, no C++ or
+ * framework types.  Every call returns an int status (DI_OK or a negative code)
+ * and never throws or aborts across the boundary.  di_last_error() returns a
+ * thread-local message for the last failure.
+ *
+ * Problem (Hong, Huynh & Mathieu, "D-Iteration: diffusion approach for solving
+ * PageRank", Section 2.1): for a directed graph with weights w(j->i) > 0,
+ *     P[i][j] = w(j->i) / s_j,   s_j = sum of j's out-weights      (equation def-p)
+ * (1/out(j) when unweighted; a dangling node j has a null column), solve
+ *     x = d P x + (1 - d) Z,     0 < d < 1,  Z >= 0                 (equation pagerank-pf)
+ *
+ * D-Iteration (Section 3.1, equation defF): fluid F_0 = (1-d) Z, history H_0 = 0;
+ * diffusing node i moves its fluid f into H_i and adds d f P e_i to F.  H converges
+ * to x and |x - H|_1 <= |F|_1 / (1-d) (Theorem 1, equation SL).  Power iteration
+ * (Section 2.2): x_{k+1} = d P x_k + (1-d) Z.
+ *
+ * Thread safety: one context is used by one host thread at a time; independent
+ * contexts are independent.  All device work of a context runs on its stream.
+ */
+#ifndef DI_API_H_
+#define DI_API_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DI_OK 0
+#define DI_EINVAL (-1)   /* invalid argument; nothing was changed */
+#define DI_ENOMEM (-2)   /* device or host allocation failed */
+#define DI_EHIP (-3)     /* a HIP runtime call failed */
+#define DI_ENOCONV (-4)  /* sweep budget spent before the tolerance; state kept, call again to continue */
+#define DI_ESTATE (-5)   /* call not valid in the context's current state */
+#define DI_ENUMERIC (-6) /* non-finite or out-of-range value met in the residual */
+
+typedef struct di_ctx di_ctx; /* opaque; owns every device buffer it allocates */
+
+/*
+ * Input graph as out-adjacency CSR (rows = sources).
+ *   out_ptr : n+1 int64, out_ptr[0] = 0, non-decreasing, out_ptr[n] = m
+ *   out_idx : m int32 targets in [0, n); self-loops and repeated edges are allowed
+ *             and count with multiplicity (they add to P[i][j] and to s_j)
+ *   w       : m float32 weights, > 0 and finite, or NULL for unweighted
+ *   on_device : 0 = host arrays, 1 = device arrays; either way they are only read
+ *             during di_init and the caller keeps ownership.
+ */
+typedef struct {
+    int64_t n;
+    int64_t m;
+    const int64_t *out_ptr;
+    const int32_t *out_idx;
+    const float *w;
+    int on_device;
+} di_csr;
+
+/* loop_mode values */
+#define DI_LOOP_STREAM 0 /* sweeps launched on the stream, host checks every sweeps_per_sync */
+#define DI_LOOP_GRAPH 1  /* chunks of sweeps captured once into a HIP graph and replayed */
+
+/*
+ * Options (pass NULL for the defaults given in brackets).
+ *   fluid_fp32     : 1 = fluid F stored and pushed in float; history H, residual and
+ *                    leak stay double [0]
+ *   theta          : frontier scale; a node is active when |F_i| >= theta * |F|_1 / n
+ *                    (the DI-argmax rule of Section 3.4 applied per sweep) [1.0]
+ *   max_sweeps     : sweep (or iteration) budget per di_diffuse / di_power call [100000]
+ *   deterministic  : 1 = synchronous sweeps with snapshot semantics and ordered
+ *                    accumulation (bit-reproducible, slower) [0]
+ *   range_log2     : block-local range size 2^range_log2 nodes, 8..16 (0 = auto)
+ *   inner_rounds   : block-local diffusion rounds per sweep, 1..64 (0 = auto)
+ *   k              : number of right-hand sides (columns of Z), 1..64 [1]
+ *   n_graphs       : > 1 declares the graph a block-diagonal union of independent
+ *                    graphs whose node ranges are given by graph_ptr [1]
+ *   graph_ptr      : host array of n_graphs+1 node offsets (0 = first, n = last)
+ *   loop_mode      : DI_LOOP_STREAM or DI_LOOP_GRAPH [DI_LOOP_STREAM]
+ *   sweeps_per_sync: sweeps enqueued between host convergence checks (0 = auto)
+ *   timing         : 1 = bracket every sweep (or iteration) kernel with HIP events and
+ *                    keep the summed device time (di_info DI_INFO_KERNEL_NS) [0]
+ *   normalized_stop: 1 = stop on |F|_1 / (1 - d - d l/|Z|_1) instead of |F|_1 / (1-d)
+ *                    (implicit completion, Section 3.3) [0]
+ *   stream         : hipStream_t to run on; NULL = the null stream
+ */
+typedef struct {
+    int fluid_fp32;
+    double theta;
+    int64_t max_sweeps;
+    int deterministic;
+    int range_log2;
+    int inner_rounds;
+    int k;
+    int64_t n_graphs;
+    const int64_t *graph_ptr;
+    int loop_mode;
+    int sweeps_per_sync;
+    int normalized_stop;
+    int timing;
+    void *stream;
+} di_opts;
+
+/* Statistics of the last di_diffuse / di_power / di_adjoint call. */
+typedef struct {
+    int64_t sweeps;        /* sweeps (DI) or iterations (PI) run by this call */
+    int64_t edge_updates;  /* edge pushes (DI) or m * iterations (PI) */
+    int64_t node_updates;  /* elementary diffusions (DI) or n * iterations (PI) */
+    double residual;       /* DI: |F|_1 incl. fluid in flight; PI: |x_{k+1} - x_k|_1;
+                              with k > 1 or n_graphs > 1: the largest per-column/graph value */
+    double bound;          /* certified distance: residual / (1-d) (Theorem 1);
+                              adjoint: max|F| / (1-d) */
+    double bound_norm;     /* residual / (1 - d - d l/|Z|_1): distance of the normalised result (Section 3.3) */
+    double leak;           /* l: fluid diffused at dangling nodes (Section 3.3) */
+    double ms;             /* device time of the call (HIP events on the context's stream) */
+    int converged;         /* 1 if every column/graph met the tolerance */
+} di_stats;
+
+/*
+ * Create a context for graph g, damping d in (0,1) and default distribution Z.
+ *   Z : host array, n x k column-major, every entry >= 0 and finite, each column
+ *       with a positive sum; NULL = uniform 1/n per column, or 1/n_g on each graph g
+ *       of a union.
+ * Builds on the device: IN adjacency (stable counting sort of OUT by target), 1/s_j,
+ * degree-binned row blocks and the block-local / cross-range edge split, then sets
+ * F = (1-d) Z, H = 0.  Errors: DI_EINVAL (bad sizes, non-monotone out_ptr, index out
+ * of range, w <= 0 or non-finite, d outside (0,1), bad Z or options), DI_ENOMEM, DI_EHIP.
+ * On error *ctx is set to NULL.
+ */
+int di_init(di_ctx **ctx, const di_csr *g, double d, const double *Z, const di_opts *o);
+
+/*
+ * D-Iteration sweeps (Section 3.1) until the certified L1 bound |F|_1 / (1-d) of every
+ * column (graph) is <= tol (Theorem 1), or max_sweeps sweeps were run (DI_ENOCONV; the
+ * state is kept and a further call continues from it).  tol must be > 0.
+ */
+int di_diffuse(di_ctx *ctx, double tol, di_stats *st);
+
+/*
+ * Power iteration x_{k+1} = d P x_k + (1-d) Z (Section 2.2) from x_0 = 0, until
+ * |x_{k+1} - x_k|_1 / (1-d) <= tol; that quantity bounds |x - x_k|_1 because
+ * x - x_k = (I - dP)^{-1} (x_{k+1} - x_k) and |P|_1 <= 1.  Independent of the DI state.
+ * Single right-hand side, single graph only (DI_EINVAL otherwise).
+ */
+int di_power(di_ctx *ctx, double tol, di_stats *st);
+
+/*
+ * Adjoint of the converged solve: with g = dL/dx, computes lambda = (I - d P^T)^{-1} g
+ * by diffusing signed fluid on the transposed matrix until max|F| / (1-d) <= tol_inf
+ * (|P^T|_inf <= 1 because every column of P sums to at most 1, Section 2.1), then
+ *   dZ[i] = (1-d) lambda_i
+ *   dw[e] = (d x_j / s_j) (lambda_i - mu_j),  e = j -> i in OUT order,
+ *           mu_j = sum over j's out-edges e' of P_{e'} lambda_{target(e')}
+ * with x the raw history H of the last di_diffuse.  g, dZ (n doubles) and dw (m
+ * doubles, may be NULL) are host arrays (on_device = 0) or device arrays (1).
+ * Requires a converged di_diffuse (DI_ESTATE otherwise); k = 1, single graph.
+ */
+int di_adjoint(di_ctx *ctx, const double *g, double tol_inf, double *dZ, double *dw, int on_device, di_stats *st);
+
+/* what values for di_read (sizes in elements; k = columns) */
+#define DI_X_RAW 0     /* H (double, n*k, column-major): the raw D-Iteration result */
+#define DI_X_NORM 1    /* (1-d)/(1-d-d l/|Z|_1) H per column: the solution completed by Z/|Z|_1
+                          at dangling nodes (Section 3.3; the paper's (1-d)/(1-d-d l) when |Z|_1 = 1) */
+#define DI_F 2         /* fluid F as double, n*k column-major, fluid in flight delivered */
+#define DI_H 3         /* same as DI_X_RAW */
+#define DI_LAMBDA 4    /* adjoint lambda (double, n) */
+#define DI_X_PI 5      /* power-iteration result (double, n) */
+#define DI_IN_PTR 6    /* IN adjacency row pointers (int64, n+1) */
+#define DI_IN_IDX 7    /* IN adjacency sources (int32, m) */
+#define DI_INV_S 8     /* 1/s_j (double, n; 0 for dangling nodes) */
+#define DI_FRONTIER 9  /* deterministic mode: ascending active set of the last sweep
+                          (int64 count followed by that many int32 indices; dst holds n+2 int32) */
+#define DI_RESIDUALS 10 /* per column (or graph) |F|_1 (double, k or n_graphs) */
+#define DI_LEAKS 11    /* per column l (double, k) */
+/* Copy a result into dst (host if dst_on_device = 0, device otherwise). */
+int di_read(di_ctx *ctx, int what, void *dst, int dst_on_device);
+
+/* Back to F = (1-d) Z, H = 0, l = 0 (graph and PI state kept). */
+int di_reset(di_ctx *ctx);
+
+/*
+ * Checkpoint (H, F, l, sweep count) to a file / restore it into a context built on
+ * the same graph, d and options.  Equation HnFn holds for any stopping point, so a
+ * restored run continues exactly.  DI_EINVAL on a mismatching file.
+ */
+int di_save(di_ctx *ctx, const char *path);
+int di_load(di_ctx *ctx, const char *path);
+
+/* info keys for di_info */
+#define DI_INFO_N 0
+#define DI_INFO_M 1
+#define DI_INFO_K 2
+#define DI_INFO_M_LOCAL 3   /* edges whose source and target share a block-local range */
+#define DI_INFO_RANGE_LOG2 4
+#define DI_INFO_INNER_ROUNDS 5
+#define DI_INFO_FIXED_K 6   /* exponent K of the fixed-point residual (sums are exact on 2^-K) */
+#define DI_INFO_TOTAL_SWEEPS 7
+#define DI_INFO_DEVICE_BYTES 8
+#define DI_INFO_KERNEL_NS 9       /* with timing: device ns of the sweep/iteration kernels of the last call */
+#define DI_INFO_KERNEL_LAUNCHES 10/* with timing: kernels timed in the last call */
+#define DI_INFO_LOCAL_PUSHES 11   /* block-local edge pushes since the last reset */
+#define DI_INFO_REMOTE_UPDATES 12 /* nonzero cross-range deliveries since the last reset */
+#define DI_INFO_M_REMOTE 13       /* cross-range edges */
+#define DI_INFO_NRANGES 14        /* block-local ranges */
+int di_info(di_ctx *ctx, int key, int64_t *value);
+
+/* Release everything; NULL-safe. */
+int di_destroy(di_ctx *ctx);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *di_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DI_API_H_ */

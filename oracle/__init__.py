@@ -296,6 +296,12 @@ def invariant_residual(og: OGraph, d: float, F0, H, F) -> float:
     return float(np.max(np.abs(r))) if len(r) else 0.0
 
 
+def invariant_residual_l1(og: OGraph, d: float, F0, H, F) -> float:
+    """|H + F - F_0 - d P H|_1: by (I - dP)^{-1} it adds at most this / (1-d) to |x - H|_1."""
+    r = np.asarray(H) + np.asarray(F) - np.asarray(F0) - d * og.P_times(H)
+    return float(np.abs(r).sum())
+
+
 def mass_defect(og: OGraph, d: float, Z, H, F, l: float) -> float:
     """sum F + (1-d) sum H + d l - (1-d) sum Z; zero in exact arithmetic.
 

@@ -1,0 +1,188 @@
+// Shared definitions of the D-Iteration / power-iteration library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/di.h"
+
+namespace di {
+
+using u64 = unsigned long long;
+using i64 = int64_t;
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------------------
+// Errors: every failing path records a message and returns a DI_E* code.
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+
+#define DI_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            ::di::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                            __LINE__);                                                     \
+            return e_ == hipErrorOutOfMemory ? DI_ENOMEM : DI_EHIP;                        \
+        }                                                                                  \
+    } while (0)
+
+#define DI_TRY(expr)                 \
+    do {                             \
+        int s_ = (expr);             \
+        if (s_ != DI_OK) return s_;  \
+    } while (0)
+
+#define DI_LAUNCH_CHECK() DI_HIP(hipGetLastError())
+
+inline unsigned grid_for(i64 work, int per_block, i64 cap = (1ll << 30)) {
+    i64 g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-point residual sums.  A non-negative double v contributes floor(v * 2^K);
+// the sum is kept exactly in four 64-bit accumulators of 32-bit limbs, so it does
+// not depend on the order of accumulation.  The final value is rounded once to the
+// nearest double (ties to even) and scaled by 2^-K.
+// ---------------------------------------------------------------------------
+struct Limbs {
+    u64 l[4];
+};
+
+__device__ __forceinline__ void limbs_zero(Limbs &a) { a.l[0] = a.l[1] = a.l[2] = a.l[3] = 0; }
+
+// v >= 0 and v * 2^K < 2^127 (the scale leaves ten bits of headroom above any sum)
+__device__ __forceinline__ void limbs_add(Limbs &a, double v, int K) {
+    if (!(v > 0.0)) return;
+    double s = ldexp(v, K);
+    u64 hi = 0;
+    if (s >= 0x1p64) {
+        hi = (u64)(s * 0x1p-64);       // floor(s / 2^64)
+        s = s - (double)hi * 0x1p64;   // exact: the bits of s below 2^64
+    }
+    u64 lo = (u64)s;
+    a.l[0] += lo & 0xffffffffull;
+    a.l[1] += lo >> 32;
+    a.l[2] += hi & 0xffffffffull;
+    a.l[3] += hi >> 32;
+}
+
+__device__ __forceinline__ u64 wave_sum_u64(u64 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ u64 wave_max_u64(u64 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        u64 t = __shfl_xor(v, o, WAVE);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+// Inclusive prefix sum over the wave (Hillis-Steele with shuffles).
+__device__ __forceinline__ int wave_incl_scan_i32(int v) {
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int t = __shfl_up(v, o, WAVE);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Block-wide sum of limbs into four device counters (one atomic per limb per block).
+// scratch: __shared__ u64[4 * (blockDim.x / 64)].
+__device__ __forceinline__ void block_limbs_to_global(Limbs &a, u64 *scratch, u64 *dst) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.l[k] = wave_sum_u64(a.l[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) scratch[4 * w + k] = a.l[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        u64 s = 0;
+        for (int q = 0; q < nw; ++q) s += scratch[4 * q + threadIdx.x];
+        if (s) atomicAdd(dst + threadIdx.x, s);
+    }
+    __syncthreads();
+}
+
+__host__ __device__ inline double limbs_to_double_raw(u64 l0, u64 l1, u64 l2, u64 l3, int K) {
+    // carry-propagate into a 128-bit value (hi, lo)
+    u64 lo = l0 & 0xffffffffull, c = l0 >> 32;
+    u64 t = l1 + c;
+    u64 carry_hi = (t < l1) ? 1ull : 0ull;  // overflow into bit 96
+    lo |= (t & 0xffffffffull) << 32;
+    c = (t >> 32) | (carry_hi << 32);
+    t = l2 + c;
+    u64 c2 = (t < l2) ? 1ull : 0ull;
+    u64 hi = t & 0xffffffffull;
+    c = (t >> 32) | (c2 << 32);
+    t = l3 + c;
+    hi |= t << 32;
+    if (hi == 0 && lo < (1ull << 53)) return ldexp((double)lo, -K);
+    int p;  // index of the top set bit
+    if (hi) p = 64 + 63 - __builtin_clzll(hi);
+    else p = 63 - __builtin_clzll(lo);
+    int s = p - 52;  // bits dropped, s >= 1
+    u64 mant;
+    if (s >= 64) mant = hi >> (s - 64);
+    else mant = (lo >> s) | (hi << (64 - s));
+    // round bit = bit (s-1); sticky = any bit below it
+    int rb = s - 1;
+    bool round_bit = rb >= 64 ? ((hi >> (rb - 64)) & 1ull) : ((lo >> rb) & 1ull);
+    bool sticky;
+    if (rb >= 64) {
+        int b = rb - 64;
+        sticky = lo != 0 || (b > 0 && (hi & ((1ull << b) - 1)) != 0);
+    } else {
+        sticky = rb > 0 && (lo & ((1ull << rb) - 1)) != 0;
+    }
+    if (round_bit && (sticky || (mant & 1ull))) mant += 1;
+    return ldexp((double)mant, s - K);
+}
+
+// ---------------------------------------------------------------------------
+// Device control block of a single-right-hand-side solve (kept in device memory).
+// ---------------------------------------------------------------------------
+struct DevCtl {
+    u64 limbsR[2][4];   // residual accumulators, double-buffered by sweep parity
+    u64 limbsL[4];      // cumulative leak (fluid diffused at dangling nodes)
+    u64 maxbits[2];     // max |F| as ordered bit patterns, double-buffered
+    u64 nodes[2];       // diffusions in the sweep, double-buffered
+    u64 edges[2];       // edge pushes in the sweep, double-buffered
+    u64 tot_nodes, tot_edges;
+    u64 remote[2];      // nonzero cross-range deliveries in the sweep (block-local sweep)
+    u64 tot_remote;
+    u64 fcount;         // deterministic sweep: active nodes recorded so far
+    u64 fcount_last;    // active nodes of the last completed sweep
+    double R;           // residual of the current state
+    double thr;         // activity threshold of the next sweep
+    double maxF;        // max |F| of the current state
+    int done;           // tolerance met
+    int guard;          // next sweep takes every node with nonzero fluid
+    int overflow;       // fixed-point range exceeded
+    int parity;         // slot written by the next sweep
+    long long sweep;    // sweeps run since reset
+    long long budget;   // sweep limit of the running call (absolute sweep index)
+};
+
+
+}  // namespace di

@@ -1,0 +1,91 @@
+// Single right-hand-side sweep kernels: block-local D-Iteration, the deterministic
+// synchronous sweep, power iteration, and the residual / control steps.
+#pragma once
+#include "graph.h"
+
+namespace di {
+
+// Work items of the row pull (power iteration), one wavefront each:
+//   short  : <= RB_ROWS consecutive rows of <= RB_SHORT entries each, <= RB_NNZ in
+//            total, staged in LDS and folded one row per lane;
+//   vector : one row of RB_SHORT+1 .. RB_SEG entries, strided over the wave's lanes
+//            and combined by a fixed-order wave reduction;
+//   long   : one row of more than RB_SEG entries, cut into segments of RB_SEG that
+//            separate workgroups reduce first (k_pi_segments).
+constexpr int RB_ROWS = 64;
+constexpr int RB_SHORT = 64;
+constexpr int RB_NNZ = 1024;
+constexpr int RB_SEG = 32768;
+constexpr int RB_KIND_SHORT = -1;
+constexpr int RB_KIND_VECTOR = -2;
+
+struct RowBlocks {
+    i64 nrb = 0, nseg = 0;
+    i64 *start = nullptr;    // nrb+1 first rows
+    int *seg_first = nullptr;// nrb: first segment of a long row, RB_KIND_SHORT or RB_KIND_VECTOR
+    int *seg_count = nullptr;// nrb
+    i64 *seg_b = nullptr, *seg_e = nullptr;  // nseg entry ranges
+    double *partial = nullptr;                // nseg partial sums
+};
+
+int build_row_blocks(RowBlocks &rb, const i64 *d_ptr, i64 n, hipStream_t st);
+void free_row_blocks(RowBlocks &rb);
+
+struct SolveState {
+    // all pointers device; T = float when fluid_fp32 else double
+    void *F = nullptr;       // n fluid
+    void *F0 = nullptr;      // n initial fluid (1-d) Z
+    double *H = nullptr;     // n history
+    void *S[2] = {nullptr, nullptr};  // n fluid in flight to other ranges (parity by ctl->parity)
+    double *snap = nullptr;  // n deterministic sweep: pushed value per source
+    int *frontier = nullptr; // n deterministic sweep: active set of the last sweep
+    int *range_order = nullptr;  // nranges, heaviest first
+    DevCtl *ctl = nullptr;
+    // power iteration
+    double *X[2] = {nullptr, nullptr};
+    void *XT[2] = {nullptr, nullptr};
+    DevCtl *pctl = nullptr;
+    double *Z = nullptr;     // n, or nullptr when uniform
+    double zc = 0.0;         // (1-d) * (1/n) when Z is uniform
+};
+
+struct SweepParams {
+    double d = 0.85, theta = 1.0, tol = 1e-8;
+    int K = 0;
+    int fp32 = 0;
+    int rounds = 8;
+    int normalized = 0;
+    i64 n = 0;
+    double zsum = 1.0;  // normalised stop uses l / zsum
+};
+
+// Kernels launched by the solver driver (all on stream st).
+// rounds == 0 delivers the fluid in flight (runs even after convergence)
+int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int rounds, hipStream_t st);
+int set_kernel_attributes();
+int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st);
+int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st);
+int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st);
+int launch_pi_iteration(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, hipStream_t st);
+int launch_pi_init(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st);
+int launch_fill_zero(void *p, i64 bytes, hipStream_t st);
+int launch_copy_fluid_to_double(const void *F, int fp32, i64 n, double *dst, hipStream_t st);
+int launch_scaled_copy(const double *H, double scale, i64 n, double *dst, hipStream_t st);
+size_t bld_lds_bytes(int rb, int fp32);
+int bld_threads();
+
+// finalize modes
+constexpr int FIN_DI = 0;     // residual of F (+ in flight); stop on R/(1-d) or R/(1-d-dl)
+constexpr int FIN_PI = 1;     // residual |x_{k+1} - x_k|; stop on R/(1-d)
+constexpr int FIN_INIT = 2;   // like FIN_DI but does not count a sweep
+constexpr int FIN_ADJ = 3;    // adjoint: stop on max|F| / (1-d)
+constexpr int FIN_DELIVER = 4;// after delivering fluid in flight: flip parity only
+constexpr int FIN_ADJ_INIT = 5;// FIN_ADJ without counting a sweep
+
+int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevCtl *ctl, const SweepParams &p,
+                     hipStream_t st);
+int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st);
+int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
+                     hipStream_t st);
+
+}  // namespace di

@@ -1,0 +1,891 @@
+// Sweep kernels for one right-hand side.
+//
+// Block-local D-Iteration (the default sweep).  Node ids are grouped into ranges of
+// 2^rb consecutive nodes; one workgroup owns a range for the whole sweep and keeps
+// its fluid in LDS.  A sweep of a range:
+//   1. loads F of the range and adds the fluid other ranges sent in the previous
+//      sweep (a pull over the range's cross-range in-edges);
+//   2. runs up to `rounds` local rounds: every wave scans its share of the range,
+//      takes each node whose fluid is at least the sweep threshold (an elementary
+//      diffusion, Section 3.1, equation defF: f -> H_i, F_i = 0, d f P e_i pushed),
+//      pushes the local part with LDS atomics and records the cross-range part per
+//      source for delivery in the next sweep;
+//   3. writes F back and adds |F| plus the fluid in flight to the residual.
+// The identity H + F = F_0 + d P H (equation HnFn) holds whenever the fluid in
+// flight is counted as fluid, so |F|_1 (with it) still bounds |x - H|_1 (Theorem 1).
+#include "sweep.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace di {
+
+constexpr int BLD_THREADS = 1024;
+constexpr int BLD_WAVES = BLD_THREADS / WAVE;
+
+int bld_threads() { return BLD_THREADS; }
+
+size_t bld_lds_bytes(int rb, int fp32) {
+    const size_t B = (size_t)1 << rb;
+    const size_t T = fp32 ? 4 : 8;
+    return 2 * B * T + (size_t)BLD_WAVES * WAVE * (8 + 4 + 8);
+}
+
+template <typename T>
+__device__ __forceinline__ T lds_load(T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// returns false if v is NaN, infinite or beyond the fixed-point range
+__device__ __forceinline__ bool limbs_add_checked(Limbs &a, double v, int K) {
+    if (!(v == v) || !(ldexp(v, K) < 0x1p126)) return false;
+    limbs_add(a, v, K);
+    return true;
+}
+
+struct BldArgs {
+    const i64 *loc_ptr;
+    const unsigned short *loc_tgt;
+    const float *loc_w;
+    const int *rem_src;
+    const unsigned short *rem_tgt;
+    const float *rem_w;
+    const i64 *rem_base;
+    const double *inv_s;
+    const double *rw;
+    const int *range_order;
+    i64 n;
+    int rb;
+    void *F;
+    double *H;
+    void *S0, *S1;
+    DevCtl *ctl;
+    double d;
+    int K;
+    int rounds;
+    int force;  // run even when the solve is marked done (delivery of fluid in flight)
+};
+
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    DevCtl *ctl = a.ctl;
+    if (!a.force && (ctl->done || ctl->sweep >= ctl->budget)) return;
+    const int B = 1 << a.rb;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    T *Fl = reinterpret_cast<T *>(smem);
+    T *Sl = Fl + B;
+    i64 *sc_start = reinterpret_cast<i64 *>(Sl + B) + w * WAVE;
+    int *sc_off = reinterpret_cast<int *>(reinterpret_cast<i64 *>(Sl + B) + BLD_WAVES * WAVE) + w * WAVE;
+    double *sc_q =
+        reinterpret_cast<double *>(reinterpret_cast<int *>(reinterpret_cast<i64 *>(Sl + B) + BLD_WAVES * WAVE) +
+                                   BLD_WAVES * WAVE) +
+        w * WAVE;
+    __shared__ u64 red[4 * BLD_WAVES];
+    __shared__ int bad;
+
+    const int par = ctl->parity;
+    const T *Sprev = reinterpret_cast<const T *>(par ? a.S1 : a.S0);
+    T *Snext = reinterpret_cast<T *>(par ? a.S0 : a.S1);
+    T *F = reinterpret_cast<T *>(a.F);
+    const double thr = ctl->thr;
+    const int r = a.range_order[blockIdx.x];
+    const i64 base = (i64)r << a.rb;
+    const int cnt = (int)min((i64)B, a.n - base);
+    if (threadIdx.x == 0) bad = 0;
+
+    // 1. fluid of the range, plus fluid sent here by other ranges last sweep
+    for (int i = threadIdx.x; i < cnt; i += BLD_THREADS) {
+        Fl[i] = F[base + i];
+        Sl[i] = (T)0;
+    }
+    __syncthreads();
+    u64 delivered = 0;
+    {
+        // batches of REM_U entries per thread: all index loads, then all gathers, then
+        // the LDS adds, so that each thread keeps REM_U independent loads in flight
+        constexpr int REM_U = 8;
+        const i64 p0 = a.rem_base[r], p1 = a.rem_base[r + 1];
+        for (i64 pb = p0 + threadIdx.x; pb < p1; pb += (i64)BLD_THREADS * REM_U) {
+            // out-of-range slots re-read the last entry (a valid address) and add nothing
+            int src[REM_U];
+            unsigned tg[REM_U];
+            float wv[REM_U];
+#pragma unroll
+            for (int u = 0; u < REM_U; ++u) {
+                const i64 p = min(pb + (i64)u * BLD_THREADS, p1 - 1);
+                src[u] = a.rem_src[p];
+                tg[u] = (unsigned)a.rem_tgt[p];
+                wv[u] = WTD ? a.rem_w[p] : 1.0f;
+            }
+            T v[REM_U];
+#pragma unroll
+            for (int u = 0; u < REM_U; ++u) v[u] = Sprev[src[u]];
+#pragma unroll
+            for (int u = 0; u < REM_U; ++u) {
+                if (pb + (i64)u * BLD_THREADS < p1 && v[u] != (T)0) {
+                    T add = v[u];
+                    if (WTD) add = (T)((double)add * (double)wv[u]);
+                    atomicAdd(&Fl[tg[u]], add);
+                    ++delivered;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // 2. local rounds; wave w owns [my0, my1)
+    const int sub = (((cnt + BLD_WAVES - 1) / BLD_WAVES) + WAVE - 1) & ~(WAVE - 1);
+    const int my0 = w * sub, my1 = min(cnt, my0 + sub);
+    Limbs leak;
+    limbs_zero(leak);
+    u64 nodes = 0, edges = 0;
+    for (int round = 0; round < a.rounds; ++round) {
+        bool any = false;
+        for (int c = my0; c < my1; c += WAVE) {
+            const int i = c + lane;
+            double f = 0.0;
+            if (i < my1) {
+                T v = lds_load(&Fl[i]);
+                if (v != (T)0 && fabs((double)v) >= thr) f = (double)atomicExch(&Fl[i], (T)0);
+            }
+            if (__ballot(f != 0.0) == 0) continue;
+            any = true;
+            int dg = 0;
+            i64 st = 0;
+            double q = 0.0;
+            if (f != 0.0) {
+                const i64 gi = base + i;
+                a.H[gi] += f;
+                const double inv = a.inv_s[gi];
+                if (inv == 0.0) {
+                    if (!limbs_add_checked(leak, fabs(f), a.K)) bad = 1;
+                } else {
+                    q = (a.d * f) * inv;
+                    if (a.rw[gi] > 0.0) Sl[i] = (T)((double)Sl[i] + q);
+                    st = a.loc_ptr[gi];
+                    dg = (int)(a.loc_ptr[gi + 1] - st);
+                }
+                ++nodes;
+            }
+            const int inc = wave_incl_scan_i32(dg);
+            const int total = __shfl(inc, WAVE - 1, WAVE);
+            sc_start[lane] = st;
+            sc_off[lane] = inc - dg;
+            sc_q[lane] = q;
+            wave_sync_lds();
+            edges += (lane == 0) ? (u64)total : 0ull;
+            // EDGE_U slots per lane per step: owners by binary search over the wave's
+            // exclusive degree offsets, then all target loads, then the LDS adds
+            constexpr int EDGE_U = 4;
+            for (int sb = lane; sb < total; sb += WAVE * EDGE_U) {
+                // slots past the end search and load for slot total-1 and add nothing
+                unsigned tgt[EDGE_U];
+                double val[EDGE_U];
+#pragma unroll
+                for (int u = 0; u < EDGE_U; ++u) {
+                    const int s = min(sb + u * WAVE, total - 1);
+                    int lo = 0, hi = WAVE - 1;  // last k with sc_off[k] <= s (it has a nonzero degree)
+#pragma unroll
+                    for (int it = 0; it < 6; ++it) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        const bool le = sc_off[mid] <= s;
+                        lo = le ? mid : lo;
+                        hi = le ? hi : mid - 1;
+                    }
+                    const i64 p = sc_start[lo] + (s - sc_off[lo]);
+                    tgt[u] = a.loc_tgt[p];
+                    val[u] = WTD ? sc_q[lo] * (double)a.loc_w[p] : sc_q[lo];
+                }
+#pragma unroll
+                for (int u = 0; u < EDGE_U; ++u)
+                    if (sb + u * WAVE < total) atomicAdd(&Fl[tgt[u]], (T)val[u]);
+            }
+            wave_sync_lds();
+        }
+        if (!any) break;
+    }
+    __syncthreads();
+
+    // 3. write back; residual = |F| + fluid in flight
+    Limbs R;
+    limbs_zero(R);
+    for (int i = threadIdx.x; i < cnt; i += BLD_THREADS) {
+        const T v = Fl[i];
+        const T s = Sl[i];
+        F[base + i] = v;
+        Snext[base + i] = s;
+        if (!limbs_add_checked(R, fabs((double)v), a.K)) bad = 1;
+        if (s != (T)0 && !limbs_add_checked(R, fabs((double)s) * a.rw[base + i], a.K)) bad = 1;
+    }
+    block_limbs_to_global(R, red, ctl->limbsR[0]);
+    block_limbs_to_global(leak, red, ctl->limbsL);
+    nodes = wave_sum_u64(nodes);
+    edges = wave_sum_u64(edges + delivered);
+    delivered = wave_sum_u64(delivered);
+    if (lane == 0) {
+        if (nodes) atomicAdd(&ctl->nodes[0], nodes);
+        if (edges) atomicAdd(&ctl->edges[0], edges);
+        if (delivered) atomicAdd(&ctl->remote[0], delivered);
+    }
+    if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
+}
+
+static BldArgs make_bld_args(const DevGraph &g, SolveState &s, const SweepParams &p, int rounds) {
+    BldArgs a;
+    a.loc_ptr = g.loc_ptr;
+    a.loc_tgt = g.loc_tgt;
+    a.loc_w = g.loc_w;
+    a.rem_src = g.rem_src;
+    a.rem_tgt = g.rem_tgt;
+    a.rem_w = g.rem_w;
+    a.rem_base = g.rem_base;
+    a.inv_s = g.inv_s;
+    a.rw = g.rw;
+    a.range_order = s.range_order;
+    a.n = g.n;
+    a.rb = g.rb;
+    a.F = s.F;
+    a.H = s.H;
+    a.S0 = s.S[0];
+    a.S1 = s.S[1];
+    a.ctl = s.ctl;
+    a.d = p.d;
+    a.K = p.K;
+    a.rounds = rounds;
+    a.force = rounds == 0;
+    return a;
+}
+
+int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int rounds, hipStream_t st) {
+    BldArgs a = make_bld_args(g, s, p, rounds);
+    const size_t lds = bld_lds_bytes(g.rb, p.fp32);
+    const unsigned grid = (unsigned)g.nranges;
+    if (p.fp32) {
+        if (g.weighted) k_bld_sweep<float, true><<<grid, BLD_THREADS, lds, st>>>(a);
+        else k_bld_sweep<float, false><<<grid, BLD_THREADS, lds, st>>>(a);
+    } else {
+        if (g.weighted) k_bld_sweep<double, true><<<grid, BLD_THREADS, lds, st>>>(a);
+        else k_bld_sweep<double, false><<<grid, BLD_THREADS, lds, st>>>(a);
+    }
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Control step: one thread turns the fixed-point sums into the residual, decides
+// convergence and sets the next threshold.  Flips the in-flight buffer parity.
+// ---------------------------------------------------------------------------
+struct FinArgs {
+    DevCtl *ctl;
+    double d, theta, tol, n_d, zsum;
+    int K, mode, normalized;
+};
+
+__global__ void k_finalize(FinArgs a) {
+    DevCtl *c = a.ctl;
+    if (threadIdx.x != 0) return;
+    const bool counts = a.mode == FIN_DI || a.mode == FIN_PI || a.mode == FIN_ADJ;
+    if (counts && (c->done || c->sweep >= c->budget)) return;
+    const double R = limbs_to_double_raw(c->limbsR[0][0], c->limbsR[0][1], c->limbsR[0][2], c->limbsR[0][3], a.K);
+    c->limbsR[0][0] = c->limbsR[0][1] = c->limbsR[0][2] = c->limbsR[0][3] = 0;
+    const double l = limbs_to_double_raw(c->limbsL[0], c->limbsL[1], c->limbsL[2], c->limbsL[3], a.K);
+    const double mx = __longlong_as_double((long long)c->maxbits[0]);
+    c->maxbits[0] = 0;
+    const u64 nodes = c->nodes[0], edges = c->edges[0], remote = c->remote[0];
+    c->nodes[0] = c->edges[0] = c->remote[0] = 0;
+    c->R = R;
+    c->maxF = mx;
+    if (a.mode == FIN_DELIVER) {
+        c->tot_edges += edges;
+        c->tot_remote += remote;
+        c->parity ^= 1;
+        return;
+    }
+    if (counts) {
+        c->tot_nodes += nodes;
+        c->tot_edges += edges;
+        c->tot_remote += remote;
+        c->sweep += 1;
+        c->parity ^= 1;
+        c->fcount_last = c->fcount;
+    }
+    double bound;
+    if (a.mode == FIN_ADJ || a.mode == FIN_ADJ_INIT) bound = mx / (1.0 - a.d);
+    else if (a.normalized && a.mode != FIN_PI) bound = R / (1.0 - a.d - a.d * l / a.zsum);
+    else bound = R / (1.0 - a.d);
+    if (c->overflow || !(bound == bound)) c->done = 1;
+    else if (bound <= a.tol) c->done = 1;
+    double thr = ((a.theta * R) / a.n_d) * (1.0 - 0x1p-30);
+    // a sweep that diffused nothing (possible only when theta > 1) is followed by one
+    // that takes every node with nonzero fluid
+    if (a.mode == FIN_DI && nodes == 0) thr = 0.0;
+    // deterministic sweeps: an empty active set falls back to all nonzero fluid
+    if (a.mode != FIN_PI && mx < thr) c->guard = 1;
+    else c->guard = 0;
+    c->thr = thr;
+}
+
+int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st) {
+    FinArgs a;
+    a.ctl = ctl;
+    a.d = p.d;
+    a.theta = p.theta;
+    a.tol = p.tol;
+    a.n_d = (double)p.n;
+    a.zsum = p.zsum;
+    a.K = p.K;
+    a.mode = mode;
+    a.normalized = p.normalized;
+    k_finalize<<<1, 64, 0, st>>>(a);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Residual of F (fixed point) and max |F|: initial state and deterministic sweeps.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce_F(const T *__restrict__ F, i64 n, int K, DevCtl *ctl) {
+    __shared__ u64 red[16];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    Limbs R;
+    limbs_zero(R);
+    u64 mx = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const double v = fabs((double)F[i]);
+        if (!limbs_add_checked(R, v, K)) bad = 1;
+        const u64 b = (u64)__double_as_longlong(v);
+        mx = b > mx ? b : mx;
+    }
+    block_limbs_to_global(R, red, ctl->limbsR[0]);
+    mx = wave_max_u64(mx);
+    if ((threadIdx.x & 63) == 0 && mx) atomicMax(&ctl->maxbits[0], mx);
+    if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
+}
+
+int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st) {
+    const unsigned grid = grid_for(g.n, 256, 4096);
+    if (p.fp32) k_reduce_F<float><<<grid, 256, 0, st>>>((const float *)s.F, g.n, p.K, s.ctl);
+    else k_reduce_F<double><<<grid, 256, 0, st>>>((const double *)s.F, g.n, p.K, s.ctl);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic synchronous sweep (snapshot semantics):
+//   A = { i : F_i != 0 and |F_i| >= thr } (all nonzero when guard is set);
+//   snap_i = (d f_i) inv_s_i for active non-dangling i, else 0; H_i += f_i; F_i = 0;
+//   then F_j = left fold over IN row j (ascending source) of snap_src (* w), starting
+//   from F_j, in double, rounded once to the fluid type.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_det_snapshot(T *F, double *H, double *snap, const double *__restrict__ inv_s,
+                                                      const i64 *__restrict__ out_ptr, i64 n, double d, int K,
+                                                      DevCtl *ctl, int *frontier) {
+    __shared__ u64 red[16];
+    if (ctl->done || ctl->sweep >= ctl->budget) return;
+    const double thr = ctl->thr;
+    const int guard = ctl->guard;
+    Limbs leak;
+    limbs_zero(leak);
+    u64 nodes = 0, edges = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const T v = F[i];
+        const bool act = v != (T)0 && (guard || fabs((double)v) >= thr);
+        double q = 0.0;
+        if (act) {
+            const double f = (double)v;
+            H[i] += f;
+            F[i] = (T)0;
+            const double inv = inv_s[i];
+            if (inv == 0.0) limbs_add(leak, fabs(f), K);
+            else q = (d * f) * inv;
+            ++nodes;
+            edges += (u64)(out_ptr[i + 1] - out_ptr[i]);
+            if (frontier) frontier[atomicAdd(&ctl->fcount, 1ull)] = (int)i;
+        }
+        snap[i] = q;
+    }
+    block_limbs_to_global(leak, red, ctl->limbsL);
+    nodes = wave_sum_u64(nodes);
+    edges = wave_sum_u64(edges);
+    if ((threadIdx.x & 63) == 0) {
+        if (nodes) atomicAdd(&ctl->nodes[0], nodes);
+        if (edges) atomicAdd(&ctl->edges[0], edges);
+    }
+}
+
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(256) k_det_pull(T *F, const double *__restrict__ snap, const i64 *__restrict__ in_ptr,
+                                                  const int *__restrict__ in_idx, const float *__restrict__ in_w, i64 n,
+                                                  DevCtl *ctl) {
+    if (ctl->done || ctl->sweep >= ctl->budget) return;
+    const i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double acc = (double)F[j];
+    const i64 p1 = in_ptr[j + 1];
+    for (i64 p = in_ptr[j]; p < p1; ++p) {
+        if (WTD) acc += snap[in_idx[p]] * (double)in_w[p];
+        else acc += snap[in_idx[p]];
+    }
+    F[j] = (T)acc;
+}
+
+__global__ void k_det_begin(DevCtl *ctl) {
+    if (ctl->done || ctl->sweep >= ctl->budget) return;
+    ctl->fcount = 0;
+}
+
+int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st) {
+    const unsigned grid = grid_for(g.n, 256, 8192);
+    k_det_begin<<<1, 1, 0, st>>>(s.ctl);
+    DI_LAUNCH_CHECK();
+    if (p.fp32) k_det_snapshot<float><<<grid, 256, 0, st>>>((float *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl, s.frontier);
+    else k_det_snapshot<double><<<grid, 256, 0, st>>>((double *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl, s.frontier);
+    DI_LAUNCH_CHECK();
+    const unsigned gridr = grid_for(g.n, 256);
+    if (p.fp32) {
+        if (g.weighted) k_det_pull<float, true><<<gridr, 256, 0, st>>>((float *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
+        else k_det_pull<float, false><<<gridr, 256, 0, st>>>((float *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
+    } else {
+        if (g.weighted) k_det_pull<double, true><<<gridr, 256, 0, st>>>((double *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
+        else k_det_pull<double, false><<<gridr, 256, 0, st>>>((double *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
+    }
+    DI_LAUNCH_CHECK();
+    return launch_reduce_F(g, s, p, st);
+}
+
+// ---------------------------------------------------------------------------
+// Power iteration (Section 2.2): x_{k+1} = d P x_k + (1-d) Z as a pull over IN with
+// xt_j = x_j / s_j prepared by the previous iteration.  One wave per row block:
+// the block's entries are gathered into LDS with coalesced index reads, then each
+// lane folds one row.  Long rows are summed by segments first (k_pi_segments).
+// ---------------------------------------------------------------------------
+constexpr int PI_WAVES = 4;
+
+struct PiArgs {
+    const i64 *rb_start;
+    const int *seg_first, *seg_count;
+    const i64 *seg_b, *seg_e;
+    double *partial;
+    const i64 *in_ptr;
+    const int *in_idx;
+    const float *in_w;
+    const double *inv_s;
+    const double *Z;
+    double zc;
+    double *X0, *X1;
+    void *XT0, *XT1;
+    DevCtl *ctl;
+    double d;
+    i64 n, nrb, nseg;
+    int K;
+};
+
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(256) k_pi_segments(PiArgs a) {
+    __shared__ double red[256 / WAVE];
+    DevCtl *ctl = a.ctl;
+    if (ctl->done || ctl->sweep >= ctl->budget) return;
+    const T *xt = reinterpret_cast<const T *>(ctl->parity ? a.XT1 : a.XT0);
+    const i64 sg = blockIdx.x;
+    const i64 b = a.seg_b[sg], e = a.seg_e[sg];
+    double acc = 0.0;
+    constexpr int SU = 8;
+    for (i64 pb = b + threadIdx.x; pb < e; pb += (i64)blockDim.x * SU) {
+        int src[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) src[u] = a.in_idx[min(pb + (i64)u * blockDim.x, e - 1)];
+        double v[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) v[u] = (double)xt[src[u]];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const i64 p = pb + (i64)u * blockDim.x;
+            if (p < e) acc += WTD ? v[u] * (double)a.in_w[p] : v[u];
+        }
+    }
+    acc = wave_sum_f64(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+        a.partial[sg] = s;
+    }
+}
+
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
+    __shared__ double tile[PI_WAVES][RB_NNZ];
+    __shared__ u64 red[4 * PI_WAVES];
+    __shared__ int bad;
+    DevCtl *ctl = a.ctl;
+    if (ctl->done || ctl->sweep >= ctl->budget) return;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const int par = ctl->parity;
+    const T *xt = reinterpret_cast<const T *>(par ? a.XT1 : a.XT0);
+    T *xtn = reinterpret_cast<T *>(par ? a.XT0 : a.XT1);
+    const double *x = par ? a.X1 : a.X0;
+    double *xn = par ? a.X0 : a.X1;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    const i64 rbk = (i64)blockIdx.x * PI_WAVES + w;
+    Limbs R;
+    limbs_zero(R);
+    if (rbk < a.nrb) {
+        const i64 r0 = a.rb_start[rbk], r1 = a.rb_start[rbk + 1];
+        const int sf = a.seg_first[rbk];
+        double acc = 0.0;
+        i64 row = -1;
+        if (sf >= 0) {
+            if (lane == 0) {
+                row = r0;
+                const int sc = a.seg_count[rbk];
+                for (int k = 0; k < sc; ++k) acc += a.partial[sf + k];
+            }
+        } else if (sf == RB_KIND_VECTOR) {
+            // one row over the wave: lane l sums entries l, l+64, ... in order, then a
+            // fixed butterfly combines the lanes
+            const i64 e0 = a.in_ptr[r0], e1 = a.in_ptr[r0 + 1];
+            constexpr int VU = 16;
+            for (i64 eb = e0 + lane; eb < e1; eb += (i64)WAVE * VU) {
+                int src[VU];
+#pragma unroll
+                for (int u = 0; u < VU; ++u) src[u] = a.in_idx[min(eb + (i64)u * WAVE, e1 - 1)];
+                double v[VU];
+#pragma unroll
+                for (int u = 0; u < VU; ++u) v[u] = (double)xt[src[u]];
+#pragma unroll
+                for (int u = 0; u < VU; ++u) {
+                    const i64 p = eb + (i64)u * WAVE;
+                    if (p < e1) acc += WTD ? v[u] * (double)a.in_w[p] : v[u];
+                }
+            }
+            acc = wave_sum_f64(acc);
+            if (lane == 0) row = r0;
+        } else {
+            const i64 e0 = a.in_ptr[r0], e1 = a.in_ptr[r1];
+            const int len = (int)(e1 - e0);
+            // stage the block's entries (at most RB_NNZ = 16 per lane): all index loads
+            // first, then all gathers
+            constexpr int PU = RB_NNZ / WAVE;
+            if (len > 0) {
+                // slots past the end re-read entry len-1 (a valid address) and store nothing
+                int src[PU];
+#pragma unroll
+                for (int u = 0; u < PU; ++u) src[u] = a.in_idx[e0 + min(u * WAVE + lane, len - 1)];
+                double v[PU];
+#pragma unroll
+                for (int u = 0; u < PU; ++u) v[u] = (double)xt[src[u]];
+#pragma unroll
+                for (int u = 0; u < PU; ++u) {
+                    const int k = u * WAVE + lane;
+                    if (k < len) tile[w][k] = WTD ? v[u] * (double)a.in_w[e0 + k] : v[u];
+                }
+            }
+            wave_sync_lds();
+            if (r0 + lane < r1) {
+                row = r0 + lane;
+                const int kb = (int)(a.in_ptr[row] - e0), ke = (int)(a.in_ptr[row + 1] - e0);
+                for (int k = kb; k < ke; ++k) acc += tile[w][k];
+            }
+        }
+        if (row >= 0) {
+            const double y = a.d * acc + (a.Z ? (1.0 - a.d) * a.Z[row] : a.zc);
+            xn[row] = y;
+            xtn[row] = (T)(y * a.inv_s[row]);
+            if (!limbs_add_checked(R, fabs(y - x[row]), a.K)) bad = 1;
+        }
+    }
+    block_limbs_to_global(R, red, ctl->limbsR[0]);
+    if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
+}
+
+static PiArgs make_pi_args(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p) {
+    PiArgs a;
+    a.rb_start = rb.start;
+    a.seg_first = rb.seg_first;
+    a.seg_count = rb.seg_count;
+    a.seg_b = rb.seg_b;
+    a.seg_e = rb.seg_e;
+    a.partial = rb.partial;
+    a.in_ptr = g.in_ptr;
+    a.in_idx = g.in_idx;
+    a.in_w = g.in_w;
+    a.inv_s = g.inv_s;
+    a.Z = s.Z;
+    a.zc = s.zc;
+    a.X0 = s.X[0];
+    a.X1 = s.X[1];
+    a.XT0 = s.XT[0];
+    a.XT1 = s.XT[1];
+    a.ctl = s.pctl;
+    a.d = p.d;
+    a.n = g.n;
+    a.nrb = rb.nrb;
+    a.nseg = rb.nseg;
+    a.K = p.K;
+    return a;
+}
+
+int launch_pi_iteration(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, hipStream_t st) {
+    PiArgs a = make_pi_args(g, rb, s, p);
+    if (rb.nseg > 0) {
+        if (p.fp32) {
+            if (g.weighted) k_pi_segments<float, true><<<(unsigned)rb.nseg, 256, 0, st>>>(a);
+            else k_pi_segments<float, false><<<(unsigned)rb.nseg, 256, 0, st>>>(a);
+        } else {
+            if (g.weighted) k_pi_segments<double, true><<<(unsigned)rb.nseg, 256, 0, st>>>(a);
+            else k_pi_segments<double, false><<<(unsigned)rb.nseg, 256, 0, st>>>(a);
+        }
+        DI_LAUNCH_CHECK();
+    }
+    const unsigned grid = grid_for(rb.nrb, PI_WAVES);
+    if (p.fp32) {
+        if (g.weighted) k_pi_rows<float, true><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+        else k_pi_rows<float, false><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+    } else {
+        if (g.weighted) k_pi_rows<double, true><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+        else k_pi_rows<double, false><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+    }
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+__global__ void k_fill_bytes_zero(unsigned *p, i64 words) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (i64)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+int launch_fill_zero(void *p, i64 bytes, hipStream_t st) {
+    const i64 words = (bytes + 3) / 4;
+    k_fill_bytes_zero<<<grid_for(words, 256, 8192), 256, 0, st>>>((unsigned *)p, words);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+int launch_pi_init(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st) {
+    DI_TRY(launch_fill_zero(s.X[0], g.n * 8, st));
+    DI_TRY(launch_fill_zero(s.X[1], g.n * 8, st));
+    DI_TRY(launch_fill_zero(s.XT[0], g.n * (p.fp32 ? 4 : 8), st));
+    DI_TRY(launch_fill_zero(s.XT[1], g.n * (p.fp32 ? 4 : 8), st));
+    return DI_OK;
+}
+
+template <typename T>
+__global__ void k_to_double(const T *__restrict__ src, i64 n, double *dst) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+int launch_copy_fluid_to_double(const void *F, int fp32, i64 n, double *dst, hipStream_t st) {
+    if (fp32) k_to_double<float><<<grid_for(n, 256, 8192), 256, 0, st>>>((const float *)F, n, dst);
+    else k_to_double<double><<<grid_for(n, 256, 8192), 256, 0, st>>>((const double *)F, n, dst);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+__global__ void k_scaled_copy(const double *__restrict__ src, double scale, i64 n, double *dst) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        dst[i] = scale * src[i];
+}
+
+int launch_scaled_copy(const double *H, double scale, i64 n, double *dst, hipStream_t st) {
+    k_scaled_copy<<<grid_for(n, 256, 8192), 256, 0, st>>>(H, scale, n, dst);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Row blocks (host partition of a row-pointer array copied from the device).
+// ---------------------------------------------------------------------------
+int build_row_blocks(RowBlocks &rb, const i64 *d_ptr, i64 n, hipStream_t st) {
+    std::vector<i64> ptr((size_t)n + 1);
+    DI_HIP(hipMemcpyAsync(ptr.data(), d_ptr, sizeof(i64) * (size_t)(n + 1), hipMemcpyDeviceToHost, st));
+    DI_HIP(hipStreamSynchronize(st));
+    std::vector<i64> start;
+    std::vector<int> sf, sc;
+    std::vector<i64> sb, se;
+    i64 r = 0;
+    while (r < n) {
+        const i64 len = ptr[r + 1] - ptr[r];
+        if (len > RB_SEG) {
+            start.push_back(r);
+            sf.push_back((int)sb.size());
+            int cnt = 0;
+            for (i64 b = ptr[r]; b < ptr[r + 1]; b += RB_SEG) {
+                sb.push_back(b);
+                se.push_back(std::min(b + RB_SEG, ptr[r + 1]));
+                ++cnt;
+            }
+            sc.push_back(cnt);
+            ++r;
+            continue;
+        }
+        if (len > RB_SHORT) {
+            start.push_back(r);
+            sf.push_back(RB_KIND_VECTOR);
+            sc.push_back(0);
+            ++r;
+            continue;
+        }
+        const i64 r0 = r;
+        while (r < n && r - r0 < RB_ROWS && ptr[r + 1] - ptr[r] <= RB_SHORT && ptr[r + 1] - ptr[r0] <= RB_NNZ) ++r;
+        start.push_back(r0);
+        sf.push_back(RB_KIND_SHORT);
+        sc.push_back(0);
+    }
+    start.push_back(n);
+    rb.nrb = (i64)sf.size();
+    rb.nseg = (i64)sb.size();
+    DI_HIP(hipMalloc((void **)&rb.start, sizeof(i64) * start.size()));
+    DI_HIP(hipMalloc((void **)&rb.seg_first, sizeof(int) * std::max<size_t>(sf.size(), 1)));
+    DI_HIP(hipMalloc((void **)&rb.seg_count, sizeof(int) * std::max<size_t>(sc.size(), 1)));
+    DI_HIP(hipMalloc((void **)&rb.seg_b, sizeof(i64) * std::max<size_t>(sb.size(), 1)));
+    DI_HIP(hipMalloc((void **)&rb.seg_e, sizeof(i64) * std::max<size_t>(se.size(), 1)));
+    DI_HIP(hipMalloc((void **)&rb.partial, sizeof(double) * std::max<size_t>(sb.size(), 1)));
+    DI_HIP(hipMemcpyAsync(rb.start, start.data(), sizeof(i64) * start.size(), hipMemcpyHostToDevice, st));
+    if (!sf.empty()) {
+        DI_HIP(hipMemcpyAsync(rb.seg_first, sf.data(), sizeof(int) * sf.size(), hipMemcpyHostToDevice, st));
+        DI_HIP(hipMemcpyAsync(rb.seg_count, sc.data(), sizeof(int) * sc.size(), hipMemcpyHostToDevice, st));
+    }
+    if (!sb.empty()) {
+        DI_HIP(hipMemcpyAsync(rb.seg_b, sb.data(), sizeof(i64) * sb.size(), hipMemcpyHostToDevice, st));
+        DI_HIP(hipMemcpyAsync(rb.seg_e, se.data(), sizeof(i64) * se.size(), hipMemcpyHostToDevice, st));
+    }
+    DI_HIP(hipStreamSynchronize(st));
+    return DI_OK;
+}
+
+void free_row_blocks(RowBlocks &rb) {
+    void *ps[] = {rb.start, rb.seg_first, rb.seg_count, rb.seg_b, rb.seg_e, rb.partial};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    rb = RowBlocks{};
+}
+
+}  // namespace di
+
+namespace di {
+
+int set_kernel_attributes() {
+    static bool done = false;
+    if (done) return DI_OK;
+    const int maxb = 160 * 1024 - 2048;
+    DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
+    DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
+    DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
+    DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
+    done = true;
+    return DI_OK;
+}
+
+}  // namespace di
+
+namespace di {
+
+// ---------------------------------------------------------------------------
+// Adjoint: diffusion of signed fluid on P^T.  Node i's diffusion sends
+// d f_i P[i][j] to every j with an edge j -> i; as a pull over OUT row j:
+//   F_j += sum over out-edges e of j of snap[target(e)] * P_e,  P_e = w_e / s_j,
+// with snap_i = d f_i on the active set (left fold in row order, double).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adj_snapshot(double *F, double *H, double *snap, const i64 *__restrict__ in_ptr,
+                                                      i64 n, double d, DevCtl *ctl) {
+    if (ctl->done || ctl->sweep >= ctl->budget) return;
+    const double thr = ctl->thr;
+    const int guard = ctl->guard;
+    u64 nodes = 0, edges = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const double v = F[i];
+        const bool act = v != 0.0 && (guard || fabs(v) >= thr);
+        double q = 0.0;
+        if (act) {
+            H[i] += v;
+            F[i] = 0.0;
+            q = d * v;
+            ++nodes;
+            edges += (u64)(in_ptr[i + 1] - in_ptr[i]);
+        }
+        snap[i] = q;
+    }
+    nodes = wave_sum_u64(nodes);
+    edges = wave_sum_u64(edges);
+    if ((threadIdx.x & 63) == 0) {
+        if (nodes) atomicAdd(&ctl->nodes[0], nodes);
+        if (edges) atomicAdd(&ctl->edges[0], edges);
+    }
+}
+
+template <bool WTD>
+__global__ void __launch_bounds__(256) k_adj_pull(double *F, const double *__restrict__ snap, const i64 *__restrict__ out_ptr,
+                                                  const int *__restrict__ out_idx, const float *__restrict__ w,
+                                                  const double *__restrict__ inv_s, i64 n, DevCtl *ctl) {
+    if (ctl->done || ctl->sweep >= ctl->budget) return;
+    const i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double acc = F[j];
+    const double inv = inv_s[j];
+    const i64 e1 = out_ptr[j + 1];
+    for (i64 e = out_ptr[j]; e < e1; ++e) {
+        const double P = WTD ? (double)w[e] * inv : inv;
+        acc += snap[out_idx[e]] * P;
+    }
+    F[j] = acc;
+}
+
+int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevCtl *ctl, const SweepParams &p,
+                     hipStream_t st) {
+    k_adj_snapshot<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(F, H, snap, g.in_ptr, g.n, p.d, ctl);
+    DI_LAUNCH_CHECK();
+    if (g.weighted) k_adj_pull<true><<<grid_for(g.n, 256), 256, 0, st>>>(F, snap, g.out_ptr, g.out_idx, g.w, g.inv_s, g.n, ctl);
+    else k_adj_pull<false><<<grid_for(g.n, 256), 256, 0, st>>>(F, snap, g.out_ptr, g.out_idx, g.w, g.inv_s, g.n, ctl);
+    DI_LAUNCH_CHECK();
+    k_reduce_F<double><<<grid_for(g.n, 256, 4096), 256, 0, st>>>(F, g.n, p.K, ctl);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st) {
+    k_reduce_F<double><<<grid_for(n, 256, 4096), 256, 0, st>>>(F, n, K, ctl);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+// dZ_j = (1-d) lambda_j; mu_j = left fold over OUT row j of P_e lambda_target;
+// dw_e = (d x_j inv_s_j) (lambda_target - mu_j).
+template <bool WTD>
+__global__ void __launch_bounds__(256) k_edge_grad(const i64 *__restrict__ out_ptr, const int *__restrict__ out_idx,
+                                                   const float *__restrict__ w, const double *__restrict__ inv_s,
+                                                   const double *__restrict__ x, const double *__restrict__ lam, i64 n,
+                                                   double d, double *dZ, double *dw) {
+    const i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    dZ[j] = (1.0 - d) * lam[j];
+    const i64 e0 = out_ptr[j], e1 = out_ptr[j + 1];
+    if (!dw) return;
+    const double inv = inv_s[j];
+    double mu = 0.0;
+    for (i64 e = e0; e < e1; ++e) mu += (WTD ? (double)w[e] * inv : inv) * lam[out_idx[e]];
+    const double a = d * x[j] * inv;
+    for (i64 e = e0; e < e1; ++e) dw[e] = a * (lam[out_idx[e]] - mu);
+}
+
+int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
+                     hipStream_t st) {
+    if (g.weighted) k_edge_grad<true><<<grid_for(g.n, 256), 256, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, d, dZ, dw);
+    else k_edge_grad<false><<<grid_for(g.n, 256), 256, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, d, dZ, dw);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+}  // namespace di
