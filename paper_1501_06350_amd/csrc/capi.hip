@@ -154,7 +154,7 @@ int reset_state(di_ctx *c) {
     DI_TRY(launch_fill_zero(c->s.S[1], n * T, c->st));
     DI_TRY(launch_fill_zero(c->s.ctl, sizeof(DevCtl), c->st));
     DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st));
-    DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_INIT, c->st));
+    DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_INIT, c->st, c->s.partR, c->s.nR, c->s.partC, 0));
     DI_HIP(hipStreamSynchronize(c->st));
     c->forward_converged = false;
     return DI_OK;
@@ -165,14 +165,14 @@ int enqueue_di_sweep(di_ctx *c, hipStream_t st, hipEvent_t e0 = nullptr, hipEven
     if (c->o.deterministic) DI_TRY(launch_det_sweep(c->g, c->s, c->p, st));
     else DI_TRY(launch_bld_sweep(c->g, c->s, c->p, c->rounds, st));
     if (e1) DI_HIP(hipEventRecord(e1, st));
-    return launch_finalize(c->s.ctl, c->p, FIN_DI, st);
+    return launch_finalize(c->s.ctl, c->p, FIN_DI, st, c->s.partR, c->s.nR, c->s.partC, c->s.nC);
 }
 
 int enqueue_pi_iteration(di_ctx *c, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     if (e0) DI_HIP(hipEventRecord(e0, st));
     DI_TRY(launch_pi_iteration(c->g, c->rbin, c->s, c->p, st));
     if (e1) DI_HIP(hipEventRecord(e1, st));
-    return launch_finalize(c->s.pctl, c->p, FIN_PI, st);
+    return launch_finalize(c->s.pctl, c->p, FIN_PI, st, c->s.partR, c->s.nR, c->s.partC, 0);
 }
 
 // After a synced chunk: add the device time of the steps that really ran.
@@ -254,7 +254,7 @@ int di_destroy(di_ctx *c) {
     free_row_blocks(c->rbin);
     void *ps[] = {c->s.F, c->s.F0, c->s.H, c->s.S[0], c->s.S[1], c->s.snap, c->s.frontier, c->s.range_order,
                   c->s.ctl, c->s.X[0], c->s.X[1], c->s.XT[0], c->s.XT[1], c->s.pctl, c->s.Z, c->lam,
-                  c->aF, c->asnap, c->actl};
+                  c->aF, c->asnap, c->actl, c->s.partR, c->s.partC};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     if (c->b) free_batch(c->b);
@@ -393,14 +393,17 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         return fail(DI_EHIP);
     }
 
-    // block-local range size: about 512 nodes per range on small graphs, at most what LDS holds
+    // block-local range size: unweighted graphs use the LDS-resident kernel with 2^11-node
+    // ranges; weighted graphs the largest range whose fluid fits in LDS; small graphs keep
+    // at least ~256 nodes per range so that several workgroups run
     int rbmax = c->p.fp32 ? 14 : 13;
     int rb = opt.range_log2;
     if (rb == 0) {
+        const int cap = w ? rbmax : 11;
         rb = 8;
-        while (rb < rbmax && ((i64)1 << (rb + 1)) * 256 <= n) ++rb;
+        while (rb < cap && ((i64)1 << (rb + 1)) * 256 <= n) ++rb;
     }
-    c->rounds = opt.inner_rounds ? opt.inner_rounds : 8;
+    c->rounds = opt.inner_rounds ? opt.inner_rounds : 4;
     c->p.rounds = c->rounds;
     c->spc = opt.sweeps_per_sync ? opt.sweeps_per_sync : 8;
     if ((rc = build_graph(c->g, c->g.out_ptr, c->g.out_idx, c->g.w, rb, c->st)) != DI_OK) return fail(rc);
@@ -427,6 +430,12 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
             set_error("range order upload failed");
             return fail(DI_EHIP);
         }
+    }
+
+    // per-workgroup partial sums (see PSR / PSC)
+    {
+        const i64 slots = std::max<i64>(c->g.nranges, PART_MIN);
+        if ((rc = dalloc(c, &c->s.partR, slots * PSR)) || (rc = dalloc(c, &c->s.partC, slots * PSC))) return fail(rc);
     }
 
     // initial fluid F_0 = (1-d) Z, rounded to float in the float-fluid mode; fixed-point scale
@@ -494,9 +503,8 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
     }
     DI_HIP(hipEventRecord(c->ev0, c->st));
     // recompute the residual of the current state under the new tolerance
-    DI_TRY(launch_fill_zero(c->s.ctl->limbsR, sizeof(c->s.ctl->limbsR), c->st));
     DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st));
-    DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_INIT, c->st));
+    DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_INIT, c->st, c->s.partR, c->s.nR, c->s.partC, 0));
     k_ctl_begin<<<1, 1, 0, c->st>>>(c->s.ctl, (long long)c->o.max_sweeps);
     DI_LAUNCH_CHECK();
     DI_TRY(sync_ctl(c, c->s.ctl));
@@ -526,7 +534,7 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
     }
     if (!c->o.deterministic) {  // deliver fluid still in flight so that F is complete
         DI_TRY(launch_bld_sweep(c->g, c->s, c->p, 0, c->st));
-        DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_DELIVER, c->st));
+        DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_DELIVER, c->st, c->s.partR, c->s.nR, c->s.partC, c->s.nC));
     }
     DI_HIP(hipEventRecord(c->ev1, c->st));
     DI_TRY(sync_ctl(c, c->s.ctl));
@@ -706,16 +714,19 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     DI_TRY(launch_fill_zero(c->lam, n * 8, c->st));
     DI_TRY(launch_fill_zero(c->actl, sizeof(DevCtl), c->st));
     DI_HIP(hipEventRecord(c->ev0, c->st));
-    DI_TRY(launch_reduce_double(c->aF, n, ap.K, c->actl, c->st));
+    i64 anR = 0, anC = 0;
+    DI_TRY(launch_reduce_double(c->aF, n, ap.K, c->actl, c->st, c->s.partR, &anR));
     k_ctl_begin<<<1, 1, 0, c->st>>>(c->actl, (long long)c->o.max_sweeps);
     DI_LAUNCH_CHECK();
-    DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ_INIT, c->st));  // sets done when g already meets tol
+    // sets done when g already meets the tolerance
+    DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ_INIT, c->st, c->s.partR, anR, c->s.partC, 0));
     DI_TRY(sync_ctl(c, c->actl));
     DevCtl before = *c->h_ctl;
     while (!c->h_ctl->done) {
         for (int k = 0; k < c->spc; ++k) {
-            DI_TRY(launch_adj_sweep(c->g, c->aF, c->lam, c->asnap, c->actl, ap, c->st));
-            DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ, c->st));
+            DI_TRY(launch_adj_sweep(c->g, c->aF, c->lam, c->asnap, c->actl, ap, c->st, c->s.partR, c->s.partC, &anR,
+                                    &anC));
+            DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ, c->st, c->s.partR, anR, c->s.partC, anC));
         }
         DI_TRY(sync_ctl(c, c->actl));
         const DevCtl &h = *c->h_ctl;
@@ -838,7 +849,7 @@ int di_load(di_ctx *c, const char *path) {
                                       h.limbsL[3], h.tot_nodes, h.tot_edges);
     DI_LAUNCH_CHECK();
     DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st));
-    DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_INIT, c->st));
+    DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_INIT, c->st, c->s.partR, c->s.nR, c->s.partC, 0));
     DI_HIP(hipStreamSynchronize(c->st));
     c->forward_converged = false;
     return DI_OK;

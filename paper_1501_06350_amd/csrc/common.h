@@ -106,22 +106,60 @@ __device__ __forceinline__ int wave_incl_scan_i32(int v) {
     return v;
 }
 
-// Block-wide sum of limbs into four device counters (one atomic per limb per block).
-// scratch: __shared__ u64[4 * (blockDim.x / 64)].
-__device__ __forceinline__ void block_limbs_to_global(Limbs &a, u64 *scratch, u64 *dst) {
+// Per-block partial sums.  Every workgroup that contributes to the residual or to the
+// counters of a sweep writes its own totals with plain stores into a slot of a partials
+// array; the control step adds the slots.  (Device-scope atomics from every workgroup
+// onto the same few addresses serialise and cost far more than the sweep itself.)
+//   residual slot (PSR words): 4 limb sums of |F|, max |F| as ordered bits
+//   counter slot  (PSC words): 4 limb sums of the leak, diffusions, edge pushes,
+//                              cross-range deliveries, unused
+constexpr int PSR = 5;
+constexpr int PSC = 8;
+
+// Reduce NV per-thread values over the block (bit k of MAXMASK: max instead of sum) and
+// store them to out[0..NV).  lds: u64[NV * blockDim.x / 64].  Contains barriers.
+template <int NV, unsigned MAXMASK = 0>
+__device__ __forceinline__ void block_store_partials(u64 (&v)[NV], u64 *lds, u64 *out) {
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a.l[k] = wave_sum_u64(a.l[k]);
+    for (int k = 0; k < NV; ++k) v[k] = ((MAXMASK >> k) & 1u) ? wave_max_u64(v[k]) : wave_sum_u64(v[k]);
     if (lane == 0)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) scratch[4 * w + k] = a.l[k];
+        for (int k = 0; k < NV; ++k) lds[w * NV + k] = v[k];
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if ((int)threadIdx.x < NV) {
+        const int k = threadIdx.x;
         u64 s = 0;
-        for (int q = 0; q < nw; ++q) s += scratch[4 * q + threadIdx.x];
-        if (s) atomicAdd(dst + threadIdx.x, s);
+        for (int q = 0; q < nw; ++q) {
+            const u64 x = lds[q * NV + k];
+            s = ((MAXMASK >> k) & 1u) ? (x > s ? x : s) : s + x;
+        }
+        out[k] = s;
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ void store_residual_partial(Limbs &R, u64 maxbits, u64 *lds, u64 *slot) {
+    u64 v[PSR] = {R.l[0], R.l[1], R.l[2], R.l[3], maxbits};
+    block_store_partials<PSR, 1u << 4>(v, lds, slot);
+}
+
+__device__ __forceinline__ void store_counter_partial(Limbs &leak, u64 nodes, u64 edges, u64 remote, u64 *lds,
+                                                      u64 *slot) {
+    u64 v[PSC] = {leak.l[0], leak.l[1], leak.l[2], leak.l[3], nodes, edges, remote, 0};
+    block_store_partials<PSC>(v, lds, slot);
+}
+
+// Carry-normalise limb sums so that each limb is below 2^32 (the top one keeps the rest).
+__host__ __device__ inline void limbs_normalize(u64 *l) {
+    u64 c = 0;
+    for (int k = 0; k < 3; ++k) {
+        const u64 t = l[k] + c;
+        const u64 carry_in = (t < l[k]) ? (1ull << 32) : 0ull;  // overflow of the 64-bit add
+        l[k] = t & 0xffffffffull;
+        c = (t >> 32) + carry_in;
+    }
+    l[3] += c;
 }
 
 __host__ __device__ inline double limbs_to_double_raw(u64 l0, u64 l1, u64 l2, u64 l3, int K) {
@@ -163,14 +201,9 @@ __host__ __device__ inline double limbs_to_double_raw(u64 l0, u64 l1, u64 l2, u6
 // Device control block of a single-right-hand-side solve (kept in device memory).
 // ---------------------------------------------------------------------------
 struct DevCtl {
-    u64 limbsR[2][4];   // residual accumulators, double-buffered by sweep parity
-    u64 limbsL[4];      // cumulative leak (fluid diffused at dangling nodes)
-    u64 maxbits[2];     // max |F| as ordered bit patterns, double-buffered
-    u64 nodes[2];       // diffusions in the sweep, double-buffered
-    u64 edges[2];       // edge pushes in the sweep, double-buffered
+    u64 limbsL[4];      // cumulative leak (fluid diffused at dangling nodes), normalised limbs
     u64 tot_nodes, tot_edges;
-    u64 remote[2];      // nonzero cross-range deliveries in the sweep (block-local sweep)
-    u64 tot_remote;
+    u64 tot_remote;     // nonzero cross-range deliveries (block-local sweep)
     u64 fcount;         // deterministic sweep: active nodes recorded so far
     u64 fcount_last;    // active nodes of the last completed sweep
     double R;           // residual of the current state

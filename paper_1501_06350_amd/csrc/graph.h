@@ -30,6 +30,7 @@ struct DevGraph {
     float *rem_w = nullptr;
     i64 m_rem = 0;
     i64 *loc_base = nullptr;           // nranges+1: loc_ptr at each range start
+    unsigned *deg_flags = nullptr;     // n: out-degree, bit 31 set when the node has cross-range edges
 };
 
 int scan_exclusive(const i64 *in, i64 *out, i64 count, i64 *temp, hipStream_t st);

@@ -355,6 +355,12 @@ __global__ void k_remote_scatter(const unsigned *__restrict__ tgt, const int *__
     if (rem_w) rem_w[q] = in_w[p];
 }
 
+__global__ void k_deg_flags(const i64 *__restrict__ out_ptr, const double *__restrict__ rw, i64 n, unsigned *out) {
+    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = (unsigned)(out_ptr[i + 1] - out_ptr[i]) | (rw[i] > 0.0 ? 0x80000000u : 0u);
+}
+
 // rem_base[r] = number of cross-range IN entries before range r's first row.
 __global__ void k_range_bases(const i64 *__restrict__ in_ptr, const i64 *__restrict__ pos, i64 n, i64 m,
                               i64 rem_total, int rb, i64 nranges, i64 *rem_base, const i64 *__restrict__ loc_ptr,
@@ -431,12 +437,15 @@ int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const f
     DI_TRY(dalloc(&g.rw, n));
     k_local_span<<<grid_for(n, TB), TB, 0, st>>>(d_out_ptr, d_out_idx, d_w, n, rb, loc_deg, loc_first, g.rw);
     DI_LAUNCH_CHECK();
+    DI_TRY(dalloc(&g.deg_flags, n));
+    k_deg_flags<<<grid_for(n, TB), TB, 0, st>>>(d_out_ptr, g.rw, n, g.deg_flags);
+    DI_LAUNCH_CHECK();
     DI_TRY(dalloc(&g.loc_ptr, n + 1));
     k_fill_i64<<<1, 1, 0, st>>>(loc_deg + n, 0, 1);
     DI_TRY(scan_exclusive(loc_deg, g.loc_ptr, n + 1, stemp, st));
     DI_HIP(hipMemcpyAsync(&g.m_loc, g.loc_ptr + n, sizeof(i64), hipMemcpyDeviceToHost, st));
     DI_HIP(hipStreamSynchronize(st));
-    DI_TRY(dalloc(&g.loc_tgt, g.m_loc));
+    DI_TRY(dalloc(&g.loc_tgt, g.m_loc + 8));  // padded: staged as 32-bit words
     if (g.weighted) DI_TRY(dalloc(&g.loc_w, g.m_loc));
     k_local_copy<<<grid_for(n, TB), TB, 0, st>>>(d_out_idx, d_w, loc_first, g.loc_ptr, n, rb, g.loc_tgt, g.loc_w);
     DI_LAUNCH_CHECK();
@@ -479,7 +488,8 @@ int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const f
 
 void free_graph(DevGraph &g) {
     void *ps[] = {g.in_ptr, g.in_idx, g.in_w, g.inv_s, g.rw, g.loc_ptr, g.loc_tgt, g.loc_w,
-                  g.rem_src, g.rem_tgt, g.rem_w, g.rem_base, g.loc_base, g.out_ptr, g.out_idx, g.w};
+                  g.rem_src, g.rem_tgt, g.rem_w, g.rem_base, g.loc_base, g.out_ptr, g.out_idx, g.w,
+                  g.deg_flags};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     g = DevGraph{};

@@ -47,7 +47,17 @@ struct SolveState {
     DevCtl *pctl = nullptr;
     double *Z = nullptr;     // n, or nullptr when uniform
     double zc = 0.0;         // (1-d) * (1/n) when Z is uniform
+    // per-workgroup partial sums of the last launched step (see PSR / PSC)
+    u64 *partR = nullptr, *partC = nullptr;
+    i64 nR = 0, nC = 0;
 };
+
+// grid caps of the grid-stride kernels; the partial-sum buffers hold
+// max(number of ranges, PART_MIN) slots
+constexpr int REDUCE_GRID = 4096;
+constexpr int SNAP_GRID = 8192;
+constexpr int PI_GRID = 4096;
+constexpr int PART_MIN = 8192;
 
 struct SweepParams {
     double d = 0.85, theta = 1.0, tol = 1e-8;
@@ -57,13 +67,15 @@ struct SweepParams {
     int normalized = 0;
     i64 n = 0;
     double zsum = 1.0;  // normalised stop uses l / zsum
+    int bld_v1 = 0;     // force the global-memory block-local kernel
 };
 
 // Kernels launched by the solver driver (all on stream st).
 // rounds == 0 delivers the fluid in flight (runs even after convergence)
 int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int rounds, hipStream_t st);
 int set_kernel_attributes();
-int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st);
+int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st, const u64 *partR, i64 nR,
+                    const u64 *partC, i64 nC);
 int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st);
 int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st);
 int launch_pi_iteration(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, hipStream_t st);
@@ -83,8 +95,8 @@ constexpr int FIN_DELIVER = 4;// after delivering fluid in flight: flip parity o
 constexpr int FIN_ADJ_INIT = 5;// FIN_ADJ without counting a sweep
 
 int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevCtl *ctl, const SweepParams &p,
-                     hipStream_t st);
-int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st);
+                     hipStream_t st, u64 *partR, u64 *partC, i64 *nR, i64 *nC);
+int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR);
 int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
                      hipStream_t st);
 

@@ -70,6 +70,7 @@ struct BldArgs {
     int K;
     int rounds;
     int force;  // run even when the solve is marked done (delivery of fluid in flight)
+    u64 *partR, *partC;  // per-workgroup partial sums (one slot per range)
 };
 
 template <typename T, bool WTD>
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
         reinterpret_cast<double *>(reinterpret_cast<int *>(reinterpret_cast<i64 *>(Sl + B) + BLD_WAVES * WAVE) +
                                    BLD_WAVES * WAVE) +
         w * WAVE;
-    __shared__ u64 red[4 * BLD_WAVES];
+    __shared__ u64 red[PSC * BLD_WAVES];
     __shared__ int bad;
 
     const int par = ctl->parity;
@@ -224,16 +225,8 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
         if (!limbs_add_checked(R, fabs((double)v), a.K)) bad = 1;
         if (s != (T)0 && !limbs_add_checked(R, fabs((double)s) * a.rw[base + i], a.K)) bad = 1;
     }
-    block_limbs_to_global(R, red, ctl->limbsR[0]);
-    block_limbs_to_global(leak, red, ctl->limbsL);
-    nodes = wave_sum_u64(nodes);
-    edges = wave_sum_u64(edges + delivered);
-    delivered = wave_sum_u64(delivered);
-    if (lane == 0) {
-        if (nodes) atomicAdd(&ctl->nodes[0], nodes);
-        if (edges) atomicAdd(&ctl->edges[0], edges);
-        if (delivered) atomicAdd(&ctl->remote[0], delivered);
-    }
+    store_residual_partial(R, 0, red, a.partR + (i64)blockIdx.x * PSR);
+    store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)blockIdx.x * PSC);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
 
@@ -260,11 +253,322 @@ static BldArgs make_bld_args(const DevGraph &g, SolveState &s, const SweepParams
     a.K = p.K;
     a.rounds = rounds;
     a.force = rounds == 0;
+    a.partR = s.partR;
+    a.partC = s.partC;
     return a;
 }
 
+
+// ---------------------------------------------------------------------------
+// Block-local sweep with the range's local adjacency resident in LDS (unweighted
+// graphs).  Per range the workgroup stages, with batched coalesced loads: the fluid,
+// the out-degrees (1/s_j = 1/out(j) is recomputed in double), the local row offsets
+// and as many 16-bit local targets as fit (the rest are read from global memory).
+// The local rounds then touch LDS only; the history increment of the sweep is kept
+// per node in LDS and added to H once at write-back, where the cross-range share
+// d * dH_i / out(i) of every node is also written for delivery next sweep.
+// ---------------------------------------------------------------------------
+struct Bld2Args {
+    const i64 *loc_ptr;
+    const unsigned short *loc_tgt;
+    const i64 *loc_base;
+    const unsigned *deg_flags;
+    const int *rem_src;
+    const unsigned short *rem_tgt;
+    const i64 *rem_base;
+    const double *rw;
+    const int *range_order;
+    i64 n;
+    int rb;
+    int tcap;  // local targets staged in LDS
+    void *F;
+    double *H;
+    void *S0, *S1;
+    DevCtl *ctl;
+    double d;
+    int K;
+    int rounds;
+    int force;
+    u64 *partR, *partC;
+};
+
+// LDS layout of k_bld2_sweep (bytes): F[B], dH[B] (fluid type), deg[B], off[B+1] (u32),
+// padding to 8, then per wave 64 x (q double, start u32, offset i32), then the targets.
+__host__ __device__ inline size_t bld2_scratch_offset(int B, int tsize) {
+    return ((size_t)2 * B * tsize + (size_t)4 * (2 * B + 1) + 7) & ~(size_t)7;
+}
+
+size_t bld2_fixed_lds(int rb, int fp32, int threads) {
+    return bld2_scratch_offset(1 << rb, fp32 ? 4 : 8) + (size_t)(threads / WAVE) * WAVE * (8 + 4 + 4);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    DevCtl *ctl = a.ctl;
+    if (!a.force && (ctl->done || ctl->sweep >= ctl->budget)) return;
+    const int B = 1 << a.rb;
+    const int nthr = blockDim.x, nw = nthr >> 6;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    T *Fl = reinterpret_cast<T *>(smem);
+    T *Dl = Fl + B;
+    unsigned *Deg = reinterpret_cast<unsigned *>(Dl + B);
+    unsigned *Off = Deg + B;  // B + 1 entries
+    double *sc_q_all = reinterpret_cast<double *>(smem + bld2_scratch_offset(B, (int)sizeof(T)));
+    unsigned *sc_start_all = reinterpret_cast<unsigned *>(sc_q_all + nw * WAVE);
+    int *sc_off_all = reinterpret_cast<int *>(sc_start_all + nw * WAVE);
+    unsigned short *Tg = reinterpret_cast<unsigned short *>(sc_off_all + nw * WAVE);
+    double *sc_q = sc_q_all + w * WAVE;
+    unsigned *sc_start = sc_start_all + w * WAVE;
+    int *sc_off = sc_off_all + w * WAVE;
+    __shared__ u64 red[PSC * 16];
+    __shared__ int bad;
+
+    const int par = ctl->parity;
+    const T *Sprev = reinterpret_cast<const T *>(par ? a.S1 : a.S0);
+    T *Snext = reinterpret_cast<T *>(par ? a.S0 : a.S1);
+    T *F = reinterpret_cast<T *>(a.F);
+    const double thr = ctl->thr;
+    const int r = a.range_order[blockIdx.x];
+    const i64 base = (i64)r << a.rb;
+    const int cnt = (int)min((i64)B, a.n - base);
+    const i64 lb = a.loc_base[r];
+    const int nloc = (int)(a.loc_base[r + 1] - lb);
+    const int ncap = min(nloc, a.tcap);
+    if (threadIdx.x == 0) bad = 0;
+
+    // 1. stage the range; every loop keeps SU independent loads in flight per thread
+    // (out-of-range slots load a valid clamped address and store nothing)
+    constexpr int SU = 8;
+    for (int i0 = threadIdx.x; i0 < cnt; i0 += nthr * SU) {
+        T fv[SU];
+        unsigned dv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = min(i0 + u * nthr, cnt - 1);
+            fv[u] = F[base + i];
+            dv[u] = a.deg_flags[base + i];
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = i0 + u * nthr;
+            if (i < cnt) {
+                Fl[i] = fv[u];
+                Dl[i] = (T)0;
+                Deg[i] = dv[u];
+            }
+        }
+    }
+    for (int i0 = threadIdx.x; i0 <= cnt; i0 += nthr * SU) {
+        i64 ov[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) ov[u] = a.loc_ptr[base + min(i0 + u * nthr, cnt)];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+            if (i0 + u * nthr <= cnt) Off[i0 + u * nthr] = (unsigned)(ov[u] - lb);
+    }
+    // local targets as 32-bit words from the aligned word holding target lb; target p
+    // sits at Tg[tdelta + p] (the target array is padded, so the last word is readable)
+    const int tdelta = (int)(lb & 1);
+    {
+        const unsigned *srcw = reinterpret_cast<const unsigned *>(a.loc_tgt) + (lb >> 1);
+        unsigned *Tw = reinterpret_cast<unsigned *>(Tg);
+        const int nwords = (tdelta + ncap + 1) >> 1;
+        for (int i0 = threadIdx.x; i0 < nwords; i0 += nthr * SU) {
+            unsigned tv[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) tv[u] = srcw[min(i0 + u * nthr, nwords - 1)];
+#pragma unroll
+            for (int u = 0; u < SU; ++u)
+                if (i0 + u * nthr < nwords) Tw[i0 + u * nthr] = tv[u];
+        }
+    }
+    __syncthreads();
+
+    // 2. fluid sent here by other ranges last sweep
+    u64 delivered = 0;
+    {
+        constexpr int REM_U = 8;
+        const i64 p0 = a.rem_base[r], p1 = a.rem_base[r + 1];
+        for (i64 pb = p0 + threadIdx.x; pb < p1; pb += (i64)nthr * REM_U) {
+            int src[REM_U];
+            unsigned tg[REM_U];
+#pragma unroll
+            for (int u = 0; u < REM_U; ++u) {
+                const i64 p = min(pb + (i64)u * nthr, p1 - 1);
+                src[u] = a.rem_src[p];
+                tg[u] = (unsigned)a.rem_tgt[p];
+            }
+            T v[REM_U];
+#pragma unroll
+            for (int u = 0; u < REM_U; ++u) v[u] = Sprev[src[u]];
+#pragma unroll
+            for (int u = 0; u < REM_U; ++u) {
+                if (pb + (i64)u * nthr < p1 && v[u] != (T)0) {
+                    atomicAdd(&Fl[tg[u]], v[u]);
+                    ++delivered;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // 3. local rounds (LDS only); wave w owns [my0, my1)
+    const int sub = (((cnt + nw - 1) / nw) + WAVE - 1) & ~(WAVE - 1);
+    const int my0 = w * sub, my1 = min(cnt, my0 + sub);
+    Limbs leak;
+    limbs_zero(leak);
+    u64 nodes = 0, edges = 0;
+    for (int round = 0; round < a.rounds; ++round) {
+        bool any = false;
+        for (int c = my0; c < my1; c += WAVE) {
+            const int i = c + lane;
+            double f = 0.0;
+            if (i < my1) {
+                T v = lds_load(&Fl[i]);
+                if (v != (T)0 && fabs((double)v) >= thr) f = (double)atomicExch(&Fl[i], (T)0);
+            }
+            if (__ballot(f != 0.0) == 0) continue;
+            any = true;
+            int dg = 0;
+            unsigned st = 0;
+            double q = 0.0;
+            if (f != 0.0) {
+                Dl[i] = (T)((double)Dl[i] + f);
+                const unsigned deg = Deg[i] & 0x7fffffffu;
+                if (deg == 0) {
+                    if (!limbs_add_checked(leak, fabs(f), a.K)) bad = 1;
+                } else {
+                    q = (a.d * f) * (1.0 / (double)deg);
+                    st = Off[i];
+                    dg = (int)(Off[i + 1] - st);
+                }
+                ++nodes;
+            }
+            const int inc = wave_incl_scan_i32(dg);
+            const int total = __shfl(inc, WAVE - 1, WAVE);
+            sc_start[lane] = st;
+            sc_off[lane] = inc - dg;
+            sc_q[lane] = q;
+            wave_sync_lds();
+            edges += (lane == 0) ? (u64)total : 0ull;
+            constexpr int EDGE_U = 4;
+            for (int sb = lane; sb < total; sb += WAVE * EDGE_U) {
+                unsigned tgt[EDGE_U];
+                double val[EDGE_U];
+#pragma unroll
+                for (int u = 0; u < EDGE_U; ++u) {
+                    const int s = min(sb + u * WAVE, total - 1);
+                    int lo = 0, hi = WAVE - 1;  // last k with sc_off[k] <= s (it has a nonzero degree)
+#pragma unroll
+                    for (int it = 0; it < 6; ++it) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        const bool le = sc_off[mid] <= s;
+                        lo = le ? mid : lo;
+                        hi = le ? hi : mid - 1;
+                    }
+                    const unsigned p = sc_start[lo] + (unsigned)(s - sc_off[lo]);
+                    tgt[u] = (int)p < ncap ? (unsigned)Tg[tdelta + p] : (unsigned)a.loc_tgt[lb + p];
+                    val[u] = sc_q[lo];
+                }
+#pragma unroll
+                for (int u = 0; u < EDGE_U; ++u)
+                    if (sb + u * WAVE < total) atomicAdd(&Fl[tgt[u]], (T)val[u]);
+            }
+            wave_sync_lds();
+        }
+        if (!any) break;
+    }
+    __syncthreads();
+
+    // 4. write back: F, H += dH, cross-range share for the next sweep, residual.
+    // Untouched nodes point their H and rw loads at the range's first node (an address
+    // every thread loads), so the batch needs no branches around its loads.
+    Limbs R;
+    limbs_zero(R);
+    for (int i0 = threadIdx.x; i0 < cnt; i0 += nthr * SU) {
+        double hv[SU], rwv[SU], dh[SU];
+        T sv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = min(i0 + u * nthr, cnt - 1);
+            dh[u] = (double)Dl[i];
+            const unsigned df = Deg[i];
+            sv[u] = (dh[u] != 0.0 && (df & 0x80000000u))
+                        ? (T)((a.d * dh[u]) * (1.0 / (double)(df & 0x7fffffffu)))
+                        : (T)0;
+            hv[u] = a.H[base + (dh[u] != 0.0 ? i : 0)];
+            rwv[u] = a.rw[base + (sv[u] != (T)0 ? i : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = i0 + u * nthr;
+            if (i < cnt) {
+                const T v = Fl[i];
+                F[base + i] = v;
+                Snext[base + i] = sv[u];
+                if (dh[u] != 0.0) a.H[base + i] = hv[u] + dh[u];
+                if (!limbs_add_checked(R, fabs((double)v), a.K)) bad = 1;
+                if (sv[u] != (T)0 && !limbs_add_checked(R, fabs((double)sv[u]) * rwv[u], a.K)) bad = 1;
+            }
+        }
+    }
+    store_residual_partial(R, 0, red, a.partR + (i64)blockIdx.x * PSR);
+    store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)blockIdx.x * PSC);
+    if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
+}
+
+// Block size, target capacity and LDS bytes of k_bld2_sweep for ranges of 2^rb nodes
+// (0 if the fixed part does not fit).
+int bld2_config(int rb, int fp32, int *threads, int *tcap, size_t *lds) {
+    const int thr = rb <= 11 ? 512 : 1024;
+    const size_t fixed = bld2_fixed_lds(rb, fp32, thr);
+    // two workgroups per CU (each also holds about 1.3 KB of static LDS) when the fixed
+    // part leaves room for a useful target buffer, else one
+    const size_t budget = fixed + 2 * 8192 <= 78 * 1024 ? 78 * 1024 : 156 * 1024;
+    if (fixed + 2 * 1024 > budget) return 0;
+    *threads = thr;
+    *tcap = (int)((budget - fixed) / 2) - 2;  // two spare entries for the word-aligned staging
+    *lds = fixed + 2 * ((size_t)*tcap + 2);
+    return 1;
+}
+
 int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int rounds, hipStream_t st) {
+    int thr = 0, tcap = 0;
+    size_t lds2 = 0;
+    if (!g.weighted && !p.bld_v1 && bld2_config(g.rb, p.fp32, &thr, &tcap, &lds2)) {
+        Bld2Args b;
+        b.loc_ptr = g.loc_ptr;
+        b.loc_tgt = g.loc_tgt;
+        b.loc_base = g.loc_base;
+        b.deg_flags = g.deg_flags;
+        b.rem_src = g.rem_src;
+        b.rem_tgt = g.rem_tgt;
+        b.rem_base = g.rem_base;
+        b.rw = g.rw;
+        b.range_order = s.range_order;
+        b.n = g.n;
+        b.rb = g.rb;
+        b.tcap = tcap;
+        b.F = s.F;
+        b.H = s.H;
+        b.S0 = s.S[0];
+        b.S1 = s.S[1];
+        b.ctl = s.ctl;
+        b.d = p.d;
+        b.K = p.K;
+        b.rounds = rounds;
+        b.force = rounds == 0;
+        b.partR = s.partR;
+        b.partC = s.partC;
+        s.nR = s.nC = g.nranges;
+        if (p.fp32) k_bld2_sweep<float><<<(unsigned)g.nranges, thr, lds2, st>>>(b);
+        else k_bld2_sweep<double><<<(unsigned)g.nranges, thr, lds2, st>>>(b);
+        DI_LAUNCH_CHECK();
+        return DI_OK;
+    }
     BldArgs a = make_bld_args(g, s, p, rounds);
+    s.nR = s.nC = g.nranges;
     const size_t lds = bld_lds_bytes(g.rb, p.fp32);
     const unsigned grid = (unsigned)g.nranges;
     if (p.fp32) {
@@ -284,22 +588,43 @@ int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int
 // ---------------------------------------------------------------------------
 struct FinArgs {
     DevCtl *ctl;
+    const u64 *partR, *partC;
+    i64 nR, nC;  // slots written by the step's kernels (0: none)
     double d, theta, tol, n_d, zsum;
     int K, mode, normalized;
 };
 
-__global__ void k_finalize(FinArgs a) {
+constexpr int FIN_THREADS = 256;
+
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinArgs a) {
     DevCtl *c = a.ctl;
-    if (threadIdx.x != 0) return;
     const bool counts = a.mode == FIN_DI || a.mode == FIN_PI || a.mode == FIN_ADJ;
     if (counts && (c->done || c->sweep >= c->budget)) return;
-    const double R = limbs_to_double_raw(c->limbsR[0][0], c->limbsR[0][1], c->limbsR[0][2], c->limbsR[0][3], a.K);
-    c->limbsR[0][0] = c->limbsR[0][1] = c->limbsR[0][2] = c->limbsR[0][3] = 0;
+    // add the per-workgroup slots
+    u64 v[PSR + PSC];
+#pragma unroll
+    for (int k = 0; k < PSR + PSC; ++k) v[k] = 0;
+    for (i64 b = threadIdx.x; b < a.nR; b += FIN_THREADS) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += a.partR[b * PSR + k];
+        const u64 m = a.partR[b * PSR + 4];
+        v[4] = m > v[4] ? m : v[4];
+    }
+    for (i64 b = threadIdx.x; b < a.nC; b += FIN_THREADS) {
+#pragma unroll
+        for (int k = 0; k < PSC; ++k) v[PSR + k] += a.partC[b * PSC + k];
+    }
+    __shared__ u64 lds[(PSR + PSC) * (FIN_THREADS / WAVE)];
+    __shared__ u64 tot[PSR + PSC];
+    block_store_partials<PSR + PSC, 1u << 4>(v, lds, tot);
+    if (threadIdx.x != 0) return;
+    // tot: residual limbs 0-3, max 4, leak limbs 5-8, nodes 9, edges 10, remote 11
+    const double R = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], a.K);
+    for (int k = 0; k < 4; ++k) c->limbsL[k] += tot[5 + k];
+    limbs_normalize(c->limbsL);
     const double l = limbs_to_double_raw(c->limbsL[0], c->limbsL[1], c->limbsL[2], c->limbsL[3], a.K);
-    const double mx = __longlong_as_double((long long)c->maxbits[0]);
-    c->maxbits[0] = 0;
-    const u64 nodes = c->nodes[0], edges = c->edges[0], remote = c->remote[0];
-    c->nodes[0] = c->edges[0] = c->remote[0] = 0;
+    const double mx = __longlong_as_double((long long)tot[4]);
+    const u64 nodes = tot[9], edges = tot[10], remote = tot[11];
     c->R = R;
     c->maxF = mx;
     if (a.mode == FIN_DELIVER) {
@@ -332,9 +657,14 @@ __global__ void k_finalize(FinArgs a) {
     c->thr = thr;
 }
 
-int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st) {
+int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st, const u64 *partR, i64 nR,
+                    const u64 *partC, i64 nC) {
     FinArgs a;
     a.ctl = ctl;
+    a.partR = partR;
+    a.partC = partC;
+    a.nR = nR;
+    a.nC = nC;
     a.d = p.d;
     a.theta = p.theta;
     a.tol = p.tol;
@@ -343,7 +673,7 @@ int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st)
     a.K = p.K;
     a.mode = mode;
     a.normalized = p.normalized;
-    k_finalize<<<1, 64, 0, st>>>(a);
+    k_finalize<<<1, FIN_THREADS, 0, st>>>(a);
     DI_LAUNCH_CHECK();
     return DI_OK;
 }
@@ -352,8 +682,8 @@ int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st)
 // Residual of F (fixed point) and max |F|: initial state and deterministic sweeps.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_reduce_F(const T *__restrict__ F, i64 n, int K, DevCtl *ctl) {
-    __shared__ u64 red[16];
+__global__ void __launch_bounds__(256) k_reduce_F(const T *__restrict__ F, i64 n, int K, DevCtl *ctl, u64 *partR) {
+    __shared__ u64 red[PSR * 4];
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
@@ -366,17 +696,16 @@ __global__ void __launch_bounds__(256) k_reduce_F(const T *__restrict__ F, i64 n
         const u64 b = (u64)__double_as_longlong(v);
         mx = b > mx ? b : mx;
     }
-    block_limbs_to_global(R, red, ctl->limbsR[0]);
-    mx = wave_max_u64(mx);
-    if ((threadIdx.x & 63) == 0 && mx) atomicMax(&ctl->maxbits[0], mx);
+    store_residual_partial(R, mx, red, partR + (i64)blockIdx.x * PSR);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
 
 int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st) {
-    const unsigned grid = grid_for(g.n, 256, 4096);
-    if (p.fp32) k_reduce_F<float><<<grid, 256, 0, st>>>((const float *)s.F, g.n, p.K, s.ctl);
-    else k_reduce_F<double><<<grid, 256, 0, st>>>((const double *)s.F, g.n, p.K, s.ctl);
+    const unsigned grid = grid_for(g.n, 256, REDUCE_GRID);
+    if (p.fp32) k_reduce_F<float><<<grid, 256, 0, st>>>((const float *)s.F, g.n, p.K, s.ctl, s.partR);
+    else k_reduce_F<double><<<grid, 256, 0, st>>>((const double *)s.F, g.n, p.K, s.ctl, s.partR);
     DI_LAUNCH_CHECK();
+    s.nR = grid;
     return DI_OK;
 }
 
@@ -390,8 +719,8 @@ int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipS
 template <typename T>
 __global__ void __launch_bounds__(256) k_det_snapshot(T *F, double *H, double *snap, const double *__restrict__ inv_s,
                                                       const i64 *__restrict__ out_ptr, i64 n, double d, int K,
-                                                      DevCtl *ctl, int *frontier) {
-    __shared__ u64 red[16];
+                                                      DevCtl *ctl, int *frontier, u64 *partC) {
+    __shared__ u64 red[PSC * 4];
     if (ctl->done || ctl->sweep >= ctl->budget) return;
     const double thr = ctl->thr;
     const int guard = ctl->guard;
@@ -411,17 +740,17 @@ __global__ void __launch_bounds__(256) k_det_snapshot(T *F, double *H, double *s
             else q = (d * f) * inv;
             ++nodes;
             edges += (u64)(out_ptr[i + 1] - out_ptr[i]);
-            if (frontier) frontier[atomicAdd(&ctl->fcount, 1ull)] = (int)i;
+        }
+        if (frontier) {  // one counter update per wave: base + rank among the wave's actives
+            const u64 mask = __ballot(act);
+            u64 wbase = 0;
+            if ((threadIdx.x & 63) == 0 && mask) wbase = atomicAdd(&ctl->fcount, (u64)__popcll(mask));
+            wbase = __shfl(wbase, 0, WAVE);
+            if (act) frontier[wbase + __popcll(mask & ((1ull << (threadIdx.x & 63)) - 1ull))] = (int)i;
         }
         snap[i] = q;
     }
-    block_limbs_to_global(leak, red, ctl->limbsL);
-    nodes = wave_sum_u64(nodes);
-    edges = wave_sum_u64(edges);
-    if ((threadIdx.x & 63) == 0) {
-        if (nodes) atomicAdd(&ctl->nodes[0], nodes);
-        if (edges) atomicAdd(&ctl->edges[0], edges);
-    }
+    store_counter_partial(leak, nodes, edges, 0, red, partC + (i64)blockIdx.x * PSC);
 }
 
 template <typename T, bool WTD>
@@ -446,12 +775,13 @@ __global__ void k_det_begin(DevCtl *ctl) {
 }
 
 int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st) {
-    const unsigned grid = grid_for(g.n, 256, 8192);
+    const unsigned grid = grid_for(g.n, 256, SNAP_GRID);
     k_det_begin<<<1, 1, 0, st>>>(s.ctl);
     DI_LAUNCH_CHECK();
-    if (p.fp32) k_det_snapshot<float><<<grid, 256, 0, st>>>((float *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl, s.frontier);
-    else k_det_snapshot<double><<<grid, 256, 0, st>>>((double *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl, s.frontier);
+    if (p.fp32) k_det_snapshot<float><<<grid, 256, 0, st>>>((float *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl, s.frontier, s.partC);
+    else k_det_snapshot<double><<<grid, 256, 0, st>>>((double *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl, s.frontier, s.partC);
     DI_LAUNCH_CHECK();
+    const i64 nC = grid;
     const unsigned gridr = grid_for(g.n, 256);
     if (p.fp32) {
         if (g.weighted) k_det_pull<float, true><<<gridr, 256, 0, st>>>((float *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
@@ -461,7 +791,9 @@ int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hip
         else k_det_pull<double, false><<<gridr, 256, 0, st>>>((double *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
     }
     DI_LAUNCH_CHECK();
-    return launch_reduce_F(g, s, p, st);
+    DI_TRY(launch_reduce_F(g, s, p, st));
+    s.nC = nC;
+    return DI_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -489,6 +821,7 @@ struct PiArgs {
     double d;
     i64 n, nrb, nseg;
     int K;
+    u64 *partR;
 };
 
 template <typename T, bool WTD>
@@ -527,7 +860,7 @@ __global__ void __launch_bounds__(256) k_pi_segments(PiArgs a) {
 template <typename T, bool WTD>
 __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
     __shared__ double tile[PI_WAVES][RB_NNZ];
-    __shared__ u64 red[4 * PI_WAVES];
+    __shared__ u64 red[PSR * PI_WAVES];
     __shared__ int bad;
     DevCtl *ctl = a.ctl;
     if (ctl->done || ctl->sweep >= ctl->budget) return;
@@ -539,10 +872,10 @@ __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
     const double *x = par ? a.X1 : a.X0;
     double *xn = par ? a.X0 : a.X1;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
-    const i64 rbk = (i64)blockIdx.x * PI_WAVES + w;
     Limbs R;
     limbs_zero(R);
-    if (rbk < a.nrb) {
+    // each wave walks work items with a stride of the whole grid
+    for (i64 rbk = (i64)blockIdx.x * PI_WAVES + w; rbk < a.nrb; rbk += (i64)gridDim.x * PI_WAVES) {
         const i64 r0 = a.rb_start[rbk], r1 = a.rb_start[rbk + 1];
         const int sf = a.seg_first[rbk];
         double acc = 0.0;
@@ -606,8 +939,9 @@ __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
             xtn[row] = (T)(y * a.inv_s[row]);
             if (!limbs_add_checked(R, fabs(y - x[row]), a.K)) bad = 1;
         }
+        wave_sync_lds();  // the next item reuses this wave's tile
     }
-    block_limbs_to_global(R, red, ctl->limbsR[0]);
+    store_residual_partial(R, 0, red, a.partR + (i64)blockIdx.x * PSR);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
 
@@ -635,6 +969,7 @@ static PiArgs make_pi_args(const DevGraph &g, const RowBlocks &rb, SolveState &s
     a.nrb = rb.nrb;
     a.nseg = rb.nseg;
     a.K = p.K;
+    a.partR = s.partR;
     return a;
 }
 
@@ -650,7 +985,8 @@ int launch_pi_iteration(const DevGraph &g, const RowBlocks &rb, SolveState &s, c
         }
         DI_LAUNCH_CHECK();
     }
-    const unsigned grid = grid_for(rb.nrb, PI_WAVES);
+    const unsigned grid = grid_for(rb.nrb, PI_WAVES, PI_GRID);
+    s.nR = grid;
     if (p.fp32) {
         if (g.weighted) k_pi_rows<float, true><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
         else k_pi_rows<float, false><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
@@ -785,6 +1121,8 @@ int set_kernel_attributes() {
     DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
     DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
     DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
+    DI_HIP(hipFuncSetAttribute((const void *)k_bld2_sweep<float>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
+    DI_HIP(hipFuncSetAttribute((const void *)k_bld2_sweep<double>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
     done = true;
     return DI_OK;
 }
@@ -800,7 +1138,8 @@ namespace di {
 // with snap_i = d f_i on the active set (left fold in row order, double).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_adj_snapshot(double *F, double *H, double *snap, const i64 *__restrict__ in_ptr,
-                                                      i64 n, double d, DevCtl *ctl) {
+                                                      i64 n, double d, DevCtl *ctl, u64 *partC) {
+    __shared__ u64 red[PSC * 4];
     if (ctl->done || ctl->sweep >= ctl->budget) return;
     const double thr = ctl->thr;
     const int guard = ctl->guard;
@@ -818,12 +1157,9 @@ __global__ void __launch_bounds__(256) k_adj_snapshot(double *F, double *H, doub
         }
         snap[i] = q;
     }
-    nodes = wave_sum_u64(nodes);
-    edges = wave_sum_u64(edges);
-    if ((threadIdx.x & 63) == 0) {
-        if (nodes) atomicAdd(&ctl->nodes[0], nodes);
-        if (edges) atomicAdd(&ctl->edges[0], edges);
-    }
+    Limbs none;
+    limbs_zero(none);
+    store_counter_partial(none, nodes, edges, 0, red, partC + (i64)blockIdx.x * PSC);
 }
 
 template <bool WTD>
@@ -844,20 +1180,26 @@ __global__ void __launch_bounds__(256) k_adj_pull(double *F, const double *__res
 }
 
 int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevCtl *ctl, const SweepParams &p,
-                     hipStream_t st) {
-    k_adj_snapshot<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(F, H, snap, g.in_ptr, g.n, p.d, ctl);
+                     hipStream_t st, u64 *partR, u64 *partC, i64 *nR, i64 *nC) {
+    const unsigned gs = grid_for(g.n, 256, SNAP_GRID);
+    k_adj_snapshot<<<gs, 256, 0, st>>>(F, H, snap, g.in_ptr, g.n, p.d, ctl, partC);
     DI_LAUNCH_CHECK();
+    *nC = gs;
     if (g.weighted) k_adj_pull<true><<<grid_for(g.n, 256), 256, 0, st>>>(F, snap, g.out_ptr, g.out_idx, g.w, g.inv_s, g.n, ctl);
     else k_adj_pull<false><<<grid_for(g.n, 256), 256, 0, st>>>(F, snap, g.out_ptr, g.out_idx, g.w, g.inv_s, g.n, ctl);
     DI_LAUNCH_CHECK();
-    k_reduce_F<double><<<grid_for(g.n, 256, 4096), 256, 0, st>>>(F, g.n, p.K, ctl);
+    const unsigned gr = grid_for(g.n, 256, REDUCE_GRID);
+    k_reduce_F<double><<<gr, 256, 0, st>>>(F, g.n, p.K, ctl, partR);
     DI_LAUNCH_CHECK();
+    *nR = gr;
     return DI_OK;
 }
 
-int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st) {
-    k_reduce_F<double><<<grid_for(n, 256, 4096), 256, 0, st>>>(F, n, K, ctl);
+int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR) {
+    const unsigned gr = grid_for(n, 256, REDUCE_GRID);
+    k_reduce_F<double><<<gr, 256, 0, st>>>(F, n, K, ctl, partR);
     DI_LAUNCH_CHECK();
+    *nR = gr;
     return DI_OK;
 }
 
