@@ -1,0 +1,171 @@
+"""Adjoint diffusion and gradients on the GPU (C ABI and torch.autograd).
+
+lambda = (I - d P^T)^{-1} g by diffusion on the transposed matrix; dL/dZ = (1-d) lambda,
+dL/dw_e = (d x_j / s_j)(lambda_i - mu_j).  Checked bit-exactly against the oracle's
+transposed sweep, against dense solves, by the duality c^T x = (1-d) Z^T lambda, and by
+central finite differences of GPU forward solves on a 200-node induced subgraph.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+D = 0.85
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rand_weighted(n, seed):
+    rng = np.random.default_rng(seed)
+    deg = rng.integers(0, 8, size=n)
+    src = np.repeat(np.arange(n), deg)
+    dst = rng.integers(0, n, size=len(src))
+    w = rng.lognormal(0, 1, size=len(src)).astype(np.float32)
+    return W.from_edges(n, src, dst, w, "rand%d" % n)
+
+
+@pytest.mark.parametrize("name", ["rand3k_w", "web20k_w", "tiny5k"])
+def test_adjoint_bit_exact_vs_oracle(gpu, name):
+    g = {"rand3k_w": lambda: rand_weighted(3000, 5), "web20k_w": lambda: W.webgen(20_000, 8, weighted=True),
+         "tiny5k": lambda: W.tiny_zipf(5000, 3)}[name]()
+    say("adjoint", name)
+    og = O.OGraph.of(g)
+    Z = np.random.default_rng(1).random(g.n)
+    Z /= Z.sum()
+    c = W.normal_vector(g.n, 5)
+    y = O.SyncDI(og, D, Z)
+    y.run(1e-13)
+    lam_o, _, _, conv = O.adjoint(og, D, c, tol_inf=1e-13)
+    assert conv
+    dw_o, dZ_o = O.edge_grad(og, D, y.H, lam_o)
+    with gpu.from_graph(g, d=D, Z=Z, deterministic=True) as s:
+        s.diffuse(1e-13)
+        np.testing.assert_array_equal(s.read(gpu.H), y.H)
+        dZ, dw, st = s.adjoint(c, 1e-13)
+        assert st["converged"]
+        np.testing.assert_array_equal(s.read(gpu.LAMBDA), lam_o)
+        np.testing.assert_array_equal(dZ, dZ_o)
+        np.testing.assert_array_equal(dw, dw_o)
+
+
+def test_adjoint_vs_dense_and_fast_forward(gpu):
+    g = rand_weighted(1500, 9)
+    og = O.OGraph.of(g)
+    Z = np.full(g.n, 1.0 / g.n)
+    c = W.normal_vector(g.n, 6)
+    lam = O.dense_adjoint(og, D, c)
+    x = O.dense_solve(og, D, Z)
+    for kw in ({}, {"fluid_fp32": True}):
+        with gpu.from_graph(g, d=D, **kw) as s:
+            s.diffuse(1e-12)
+            dZ, dw, st = s.adjoint(c, 1e-12)
+            lg = s.read(gpu.LAMBDA)
+            assert np.abs(lg - lam).max() <= 1e-9 * np.abs(lam).max()
+            # L-infinity certificate of the adjoint diffusion
+            assert np.abs(lg - lam).max() <= st["bound"] + 1e-15
+            np.testing.assert_allclose(dZ, (1 - D) * lam, rtol=0, atol=1e-9 * np.abs(lam).max())
+            dw_ref, _ = O.edge_grad(og, D, x, lam)
+            rel = 1e-6 if kw else 1e-9
+            assert np.abs(dw - dw_ref).max() <= rel * np.abs(dw_ref).max()
+
+
+def test_duality_and_sampled_rows_at_scale(gpu):
+    """Config of the adjoint workload: web-like graph, n = 2M, LogNormal(0,1) weights."""
+    g = W.webgen(2_000_000, 5, weighted=True)
+    Z = np.full(g.n, 1.0 / g.n)
+    c = W.normal_vector(g.n, 5)
+    say("adjoint at n=2M, m=%d" % g.m)
+    with gpu.from_graph(g, d=D) as s:
+        st = s.diffuse(1e-11)
+        x = s.read(gpu.H)
+        dZ, dw, sta = s.adjoint(c, 1e-11)
+        lam = s.read(gpu.LAMBDA)
+    # c^T x = (1-d) Z^T lambda (both sides from the GPU; exact identity of the solutions)
+    lhs, rhs = float(c @ x), float((1 - D) * Z @ lam)
+    err_bound = np.abs(c).max() * st["bound"] + np.abs((1 - D) * Z).sum() * sta["bound"]
+    assert abs(lhs - rhs) <= err_bound + 1e-12
+    # sampled rows: lambda_i - d (P^T lambda)_i - c_i, evaluated from the OUT rows directly
+    rng = np.random.default_rng(0)
+    rows = rng.choice(g.n, 2000, replace=False)
+    for i in rows:
+        b, e = g.out_ptr[i], g.out_ptr[i + 1]
+        if e == b:
+            r = lam[i] - c[i]
+        else:
+            wv = g.w[b:e].astype(np.float64)
+            r = lam[i] - D * float((wv / wv.sum()) @ lam[g.out_idx[b:e]]) - c[i]
+        assert abs(r) <= sta["bound"] * (1 - D) * 1.0001 + 1e-12
+    # dZ is (1-d) lambda
+    np.testing.assert_allclose(dZ, (1 - D) * lam, rtol=1e-15, atol=0)
+
+
+@pytest.fixture(scope="module")
+def fd_subgraph():
+    g = W.webgen(2_000_000, 5, weighted=True)
+    sub, nodes = W.induced_bfs_subgraph(g, 200, seed=5)
+    assert sub.n == 200 and sub.m > 0
+    return sub
+
+
+def test_gradients_vs_central_differences(gpu, fd_subgraph):
+    """Finite-difference check of dL/dw and dL/dZ on the 200-node induced subgraph (f64)."""
+    g = fd_subgraph
+    say("FD subgraph n=%d m=%d" % (g.n, g.m))
+    Z = np.random.default_rng(3).random(g.n)
+    Z /= Z.sum()
+    c = W.normal_vector(g.n, 7)
+    tol = 1e-14
+
+    def loss(w, Zv):
+        with gpu.Solver(g.n, g.out_ptr, g.out_idx, w, d=D, Z=Zv, deterministic=True) as s:
+            s.diffuse(tol)
+            return float(c @ s.read(gpu.H))
+
+    with gpu.Solver(g.n, g.out_ptr, g.out_idx, g.w, d=D, Z=Z, deterministic=True) as s:
+        s.diffuse(tol)
+        dZ, dw, _ = s.adjoint(c, tol)
+    scale = np.abs(dw).max()
+    for e in range(g.m):
+        wp, wm = g.w.copy(), g.w.copy()
+        wp[e] = np.float32(float(g.w[e]) * (1 + 2.0 ** -10))
+        wm[e] = np.float32(float(g.w[e]) * (1 - 2.0 ** -10))
+        fd = (loss(wp, Z) - loss(wm, Z)) / (float(wp[e]) - float(wm[e]))
+        assert abs(fd - dw[e]) <= 1e-5 * max(abs(dw[e]), 1e-2 * scale), (e, fd, dw[e])
+    for i in range(0, g.n, 7):
+        h = 1e-5 * Z[i] + 1e-9
+        Zp, Zm = Z.copy(), Z.copy()
+        Zp[i] += h
+        Zm[i] -= h
+        fd = (loss(g.w, Zp) - loss(g.w, Zm)) / (2 * h)
+        assert abs(fd - dZ[i]) <= 1e-5 * max(abs(dZ[i]), 1e-3), (i, fd, dZ[i])
+
+
+def test_autograd_function(gpu, fd_subgraph):
+    import torch
+    from paper_1501_06350_amd.autograd import pagerank
+    g = fd_subgraph
+    dev = torch.device("cuda:0")
+    Zn = np.random.default_rng(4).random(g.n)
+    Zn /= Zn.sum()
+    Z = torch.tensor(Zn, dtype=torch.float64, device=dev, requires_grad=True)
+    w = torch.tensor(g.w, dtype=torch.float32, device=dev, requires_grad=True)
+    c = torch.tensor(W.normal_vector(g.n, 8), dtype=torch.float64, device=dev)
+    x = pagerank(Z, w, g, d=D, tol=1e-14, tol_adj=1e-14, deterministic=True)
+    L = (c * x).sum()
+    L.backward()
+    # against the C ABI adjoint directly
+    with gpu.Solver(g.n, g.out_ptr, g.out_idx, g.w, d=D, Z=Zn, deterministic=True) as s:
+        s.diffuse(1e-14)
+        dZ, dw, _ = s.adjoint(c.cpu().numpy(), 1e-14)
+    np.testing.assert_array_equal(Z.grad.cpu().numpy(), dZ)
+    np.testing.assert_array_equal(w.grad.double().cpu().numpy(), dw.astype(np.float32).astype(np.float64))
+
+    # torch.autograd.gradcheck in float64 with respect to Z
+    def f(Zt):
+        return (c * pagerank(Zt, w.detach(), g, d=D, tol=1e-14, tol_adj=1e-14, deterministic=True)).sum()
+    Zt = torch.tensor(Zn, dtype=torch.float64, device=dev, requires_grad=True)
+    assert torch.autograd.gradcheck(f, (Zt,), eps=1e-6, atol=1e-7, rtol=1e-5)
