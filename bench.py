@@ -53,7 +53,7 @@ def main():
     ap.add_argument("--n", type=int, default=50_000_000)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--fp64", action="store_true", help="double fluid instead of float")
-    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the k=64 and 256-graph legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--range-log2", type=int, default=0)
@@ -179,49 +179,97 @@ def main():
     s.close()
     del xd, xp
 
-    if args.batched:
-        try:
-            result["batched"] = bench_batched(fp32)
-        except Exception as e:  # reported, not fatal: the headline is the single solve
-            result["batched"] = {"error": str(e)[:300]}
+    if not args.no_batched:
+        for key, fn in (("batched_k64", bench_batched), ("union_256", bench_union)):
+            try:
+                result[key] = fn(fp32)
+            except Exception as e:  # reported, not fatal: the headline is the single solve
+                result[key] = {"error": str(e)[:300]}
+            log("%s: %s" % (key, json.dumps(result[key])))
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(g, args.cpu_sweeps)
     print(json.dumps(result), flush=True)
 
 
-def bench_batched(fp32):
-    """k=64 personalized PageRank on webgen(4M): one batched solve vs 64 single solves."""
-    import numpy as np
+def _timed(fn):
     import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, 1e3 * (time.perf_counter() - t)
+
+
+def bench_batched(fp32):
+    """Personalized PageRank, webgen(4M, seed 4), k=64 columns of 16 seeds each, L1 tol 1e-8
+    per column: one k=64 tile solve vs 64 single-column solves on the same resident graph
+    (di_set_z between them, outside the timed calls)."""
+    import numpy as np
     import workloads as W
     from paper_1501_06350_amd import binding as B
     g = W.webgen(4_000_000, 4)
     Z = W.ppr_Z(g.n, 64, 16, 4)
-    out = {}
-    # single solves need their own Z: one context per column (graph build excluded from timing)
-    singles = 0.0
-    for c in range(64):
-        with B.from_graph(g, d=D, Z=np.ascontiguousarray(Z[:, c]), fluid_fp32=True) as sc:
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            sc.diffuse(TOL)
-            torch.cuda.synchronize()
-            singles += time.perf_counter() - t
-    out["single_total_ms"] = round(1e3 * singles, 3)
+    out = {"workload": "webgen n=%d m=%d seed=4, k=64 x 16 seeds, %s fluid" % (g.n, g.m, "f32" if fp32 else "f64")}
+    singles, single_sweeps = 0.0, 0
+    with B.from_graph(g, d=D, Z=np.ascontiguousarray(Z[:, 0]), fluid_fp32=fp32) as sc:
+        sc.diffuse(TOL)  # warm-up
+        for c in range(64):
+            sc.set_z(np.ascontiguousarray(Z[:, c]))
+            st, ms = _timed(lambda: sc.diffuse(TOL))
+            singles += ms
+            single_sweeps += st["sweeps"]
+    out["single_total_ms"] = round(singles, 3)
+    out["single_mean_sweeps"] = round(single_sweeps / 64, 2)
+    with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=fp32) as sb:
+        sb.diffuse(TOL)  # warm-up
+        sb.reset()
+        st, ms = _timed(lambda: sb.diffuse(TOL))
+        assert st["converged"]
+    out["batched_ms"] = round(ms, 3)
+    out["speedup"] = round(singles / ms, 3)
+    out["batched_sweeps"] = st["sweeps"]
+    out["edge_column_updates"] = st["edge_updates"]
+    out["geups_edge_columns"] = round(st["edge_updates"] / (ms * 1e-3) / 1e9, 3)
+    return out
+
+
+def bench_union(fp32):
+    """256 independent webgen graphs of log-uniform size 1k..200k (seed 4), uniform Z each,
+    L1 tol 1e-8 per graph: one union solve vs 256 separate solves (all graphs resident)."""
+    import numpy as np
+    import workloads as W
+    from paper_1501_06350_amd import binding as B
+    u, gp = W.multigraph_batch(256, 4)
+    out = {"workload": "256 webgen graphs, n=%d m=%d, %s fluid" % (u.n, u.m, "f32" if fp32 else "f64")}
+    ctxs = []
     try:
-        with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=True) as sb:
-            sb.diffuse(TOL)
-            sb.reset()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            st = sb.diffuse(TOL)
-            torch.cuda.synchronize()
-            out["batched_ms"] = round(1e3 * (time.perf_counter() - t), 3)
-            out["speedup"] = round(out["single_total_ms"] / out["batched_ms"], 3)
-            out["batched_sweeps"] = st["sweeps"]
-    except B.DIError as e:
-        out["batched_error"] = str(e)[:200]
+        for q in range(256):
+            lo, hi = int(gp[q]), int(gp[q + 1])
+            ptr = u.out_ptr[lo:hi + 1] - u.out_ptr[lo]
+            idx = u.out_idx[u.out_ptr[lo]:u.out_ptr[hi]] - lo
+            s = B.Solver(hi - lo, ptr, idx, None, d=D, fluid_fp32=fp32)
+            s.diffuse(TOL)  # warm-up
+            s.reset()
+            ctxs.append(s)
+        sep = 0.0
+        for s in ctxs:
+            st, ms = _timed(lambda: s.diffuse(TOL))
+            sep += ms
+    finally:
+        for s in ctxs:
+            s.close()
+    out["separate_total_ms"] = round(sep, 3)
+    with B.Solver(u.n, u.out_ptr, u.out_idx, None, d=D, graph_ptr=gp, fluid_fp32=fp32) as su:
+        su.diffuse(TOL)
+        su.reset()
+        st, ms = _timed(lambda: su.diffuse(TOL))
+        assert st["converged"]
+        done = su.read(B.DONE_SWEEPS)
+    out["union_ms"] = round(ms, 3)
+    out["speedup"] = round(sep / ms, 3)
+    out["union_sweeps"] = st["sweeps"]
+    out["graph_sweeps_min_max"] = [int(done.min()), int(done.max())]
     return out
 
 

@@ -72,10 +72,23 @@ typedef struct {
  *                    accumulation (bit-reproducible, slower) [0]
  *   range_log2     : block-local range size 2^range_log2 nodes, 8..16 (0 = auto)
  *   inner_rounds   : block-local diffusion rounds per sweep, 1..64 (0 = auto)
- *   k              : number of right-hand sides (columns of Z), 1..64 [1]
+ *   k              : number of right-hand sides (columns of Z), 1..64 [1].  k > 1
+ *                    diffuses an n x k fluid tile (personalized PageRank, Section 2.1):
+ *                    a node is taken when any column's fluid reaches that column's
+ *                    threshold, and then every column of the row is diffused; each
+ *                    column has its own residual and stop.  Block-local options do not
+ *                    apply; di_power, di_adjoint and checkpoints are single-column only.
  *   n_graphs       : > 1 declares the graph a block-diagonal union of independent
- *                    graphs whose node ranges are given by graph_ptr [1]
- *   graph_ptr      : host array of n_graphs+1 node offsets (0 = first, n = last)
+ *                    graphs whose node ranges are given by graph_ptr [1].  Every edge
+ *                    must stay inside its graph.  Each graph g is solved as its own
+ *                    problem in the same sweeps: threshold theta |F_g|_1 / n_g, its own
+ *                    residual, leak and stop; a graph that meets the tolerance is left
+ *                    alone while the others continue.  Internally each graph starts on a
+ *                    block-local range boundary (padding nodes without edges or fluid);
+ *                    results are read back in the caller's numbering.  Not with k > 1;
+ *                    di_power, di_adjoint and checkpoints take a single graph.
+ *   graph_ptr      : host array of n_graphs+1 node offsets (0 = first, n = last),
+ *                    strictly increasing
  *   loop_mode      : DI_LOOP_STREAM or DI_LOOP_GRAPH [DI_LOOP_STREAM]
  *   sweeps_per_sync: sweeps enqueued between host convergence checks (0 = auto)
  *   timing         : 1 = bracket every sweep (or iteration) kernel with HIP events and
@@ -171,12 +184,23 @@ int di_adjoint(di_ctx *ctx, const double *g, double tol_inf, double *dZ, double 
 #define DI_FRONTIER 9  /* deterministic mode: ascending active set of the last sweep
                           (int64 count followed by that many int32 indices; dst holds n+2 int32) */
 #define DI_RESIDUALS 10 /* per column (or graph) |F|_1 (double, k or n_graphs) */
-#define DI_LEAKS 11    /* per column l (double, k) */
+#define DI_LEAKS 11    /* per column (or graph) l (double, k or n_graphs) */
+#define DI_DONE_SWEEPS 12 /* per column (or graph): total sweep count at which it met the
+                             tolerance of the last di_diffuse, -1 if it has not (int64, k or
+                             n_graphs; a single-column solve gives 1 value) */
 /* Copy a result into dst (host if dst_on_device = 0, device otherwise). */
 int di_read(di_ctx *ctx, int what, void *dst, int dst_on_device);
 
 /* Back to F = (1-d) Z, H = 0, l = 0 (graph and PI state kept). */
 int di_reset(di_ctx *ctx);
+
+/*
+ * Replace Z (host array, same layout and rules as in di_init; NULL = uniform) and reset
+ * to F = (1-d) Z, H = 0.  The graph and every device structure built from it stay, so a
+ * stream of personalized queries on one graph pays the graph build once.  DI_EINVAL
+ * on a bad Z (the context is then unchanged).
+ */
+int di_set_z(di_ctx *ctx, const double *Z);
 
 /*
  * Checkpoint (H, F, l, sweep count) to a file / restore it into a context built on
@@ -202,6 +226,7 @@ int di_load(di_ctx *ctx, const char *path);
 #define DI_INFO_REMOTE_UPDATES 12 /* nonzero cross-range deliveries since the last reset */
 #define DI_INFO_M_REMOTE 13       /* cross-range edges */
 #define DI_INFO_NRANGES 14        /* block-local ranges */
+#define DI_INFO_N_INTERNAL 15     /* nodes held on the device (n plus the padding of a union) */
 int di_info(di_ctx *ctx, int key, int64_t *value);
 
 /* Release everything; NULL-safe. */

@@ -19,13 +19,13 @@ DI_OK, DI_EINVAL, DI_ENOMEM, DI_EHIP, DI_ENOCONV, DI_ESTATE, DI_ENUMERIC = 0, -1
 STATUS_NAMES = {0: "DI_OK", -1: "DI_EINVAL", -2: "DI_ENOMEM", -3: "DI_EHIP", -4: "DI_ENOCONV", -5: "DI_ESTATE",
                 -6: "DI_ENUMERIC"}
 LOOP_STREAM, LOOP_GRAPH = 0, 1
-X_RAW, X_NORM, F, H, LAMBDA, X_PI, IN_PTR, IN_IDX, INV_S, FRONTIER, RESIDUALS, LEAKS = range(12)
+X_RAW, X_NORM, F, H, LAMBDA, X_PI, IN_PTR, IN_IDX, INV_S, FRONTIER, RESIDUALS, LEAKS, DONE_SWEEPS = range(13)
 INFO_N, INFO_M, INFO_K, INFO_M_LOCAL, INFO_RANGE_LOG2, INFO_INNER_ROUNDS, INFO_FIXED_K, INFO_TOTAL_SWEEPS, \
     INFO_DEVICE_BYTES, INFO_KERNEL_NS, INFO_KERNEL_LAUNCHES, INFO_LOCAL_PUSHES, INFO_REMOTE_UPDATES, INFO_M_REMOTE, \
-    INFO_NRANGES = range(15)
+    INFO_NRANGES, INFO_N_INTERNAL = range(16)
 
-EXPORTED = ["di_init", "di_diffuse", "di_power", "di_adjoint", "di_read", "di_reset", "di_save", "di_load",
-            "di_info", "di_destroy", "di_last_error"]
+EXPORTED = ["di_init", "di_diffuse", "di_power", "di_adjoint", "di_read", "di_reset", "di_set_z", "di_save",
+            "di_load", "di_info", "di_destroy", "di_last_error"]
 
 
 class DIError(RuntimeError):
@@ -66,6 +66,12 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError("libdi.so not found at %s: run __graft_entry__.build() first" % path)
+    # Load PyTorch's HIP runtime first when it is installed, so that the library and the
+    # tensors handed to it share one runtime (and the runtime PyTorch was built against).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     lib.di_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(DiCsr), dbl, vp, ctypes.POINTER(DiOpts)]
@@ -74,6 +80,7 @@ def load_library(path: str = LIB_PATH):
     lib.di_adjoint.argtypes = [vp, vp, dbl, vp, vp, ci, ctypes.POINTER(DiStats)]
     lib.di_read.argtypes = [vp, ci, vp, ci]
     lib.di_reset.argtypes = [vp]
+    lib.di_set_z.argtypes = [vp, vp]
     lib.di_save.argtypes = [vp, ctypes.c_char_p]
     lib.di_load.argtypes = [vp, ctypes.c_char_p]
     lib.di_info.argtypes = [vp, ci, ctypes.POINTER(i64)]
@@ -215,7 +222,9 @@ class Solver:
             cnt = int(buf[:2].view(np.int64)[0])
             return buf[2:2 + cnt].copy()
         elif what in (RESIDUALS, LEAKS):
-            shape, dt = ((max(k, self.n_graphs),) if what == RESIDUALS else (k,)), np.float64
+            shape, dt = (max(k, self.n_graphs),), np.float64
+        elif what == DONE_SWEEPS:
+            shape, dt = (max(k, self.n_graphs),), np.int64
         else:
             raise ValueError("unknown read target %d" % what)
         if out is not None and _is_torch(out):
@@ -229,6 +238,16 @@ class Solver:
 
     def reset(self):
         _check(self._lib.di_reset(self._ctx))
+
+    def set_z(self, Z=None):
+        """New distribution(s) Z (n, or n x k) on the resident graph; resets the solve."""
+        if Z is None:
+            _check(self._lib.di_set_z(self._ctx, None))
+            return
+        z = np.asfortranarray(np.asarray(Z, dtype=np.float64)).ravel(order="F")
+        if z.size != self.n * self.k:
+            raise ValueError("Z must hold n * k = %d values" % (self.n * self.k))
+        _check(self._lib.di_set_z(self._ctx, ctypes.c_void_p(z.ctypes.data)))
 
     def save(self, path: str):
         _check(self._lib.di_save(self._ctx, path.encode()))

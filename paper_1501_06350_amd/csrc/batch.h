@@ -1,5 +1,5 @@
-// Several right-hand sides (an n x k fluid tile) or a block-diagonal union of
-// independent graphs, solved in one sweep loop.
+// Several right-hand sides: an n x k fluid tile (node-major) solved in one sweep loop,
+// with a residual, threshold and stop per column.
 #pragma once
 #include "sweep.h"
 
@@ -7,11 +7,13 @@ namespace di {
 
 struct BatchState;
 
-int init_batch(BatchState *&b, const DevGraph &g, SweepParams &p, int k, const std::vector<i64> &graph_ptr,
-               const double *Z, hipStream_t st);
+// Z: n x k column-major (NULL = uniform 1/n); det = deterministic sweeps
+int init_batch(BatchState *&b, const DevGraph &g, SweepParams &p, int k, int det, const double *Z, hipStream_t st);
 int reset_batch(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st);
-int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const di_opts &o, int rounds, int spc,
-                  hipStream_t st, di_stats *stats);
+// new right-hand sides (validated by the caller; NULL = uniform), then reset
+int set_batch_z(BatchState *b, const DevGraph &g, SweepParams &p, const double *Z, hipStream_t st);
+int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const di_opts &o, int spc, hipStream_t st,
+                  di_stats *stats);
 int read_batch(BatchState *b, const DevGraph &g, const SweepParams &p, int what, void *dst, int on_device,
                hipStream_t st);
 i64 batch_sweeps(BatchState *b, hipStream_t st);

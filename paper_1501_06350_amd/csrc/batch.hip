@@ -1,25 +1,770 @@
+// Several right-hand sides: personalized PageRank for k <= 64 distributions Z_c at once
+// (Section 2.1 allows any Z; one solve per Z_c).  The fluid is an n x k tile stored
+// node-major (row i holds F_i1..F_ik), the history an n x k double tile.  One wavefront
+// owns a row and lane c is column c, so every index or weight read of a row serves all
+// k columns and every row access is one contiguous k-element vector.
+//
+// Fast sweep: a row is taken when some column's fluid reaches that column's threshold
+// theta |F_c|_1 / n; the wave then diffuses every column of the row that is still
+// running (an elementary diffusion per column, Section 3.1, equation defF): H_ic += f_c,
+// the fluid f_c is subtracted from F_ic with an atomic add (pushes that arrive
+// meanwhile stay), and d f_c P_ji is added to each successor row j with one coalesced
+// k-lane atomic add per edge.
+//
+// Deterministic sweep: per column exactly the synchronous sweep of one right-hand side
+// (snapshot of the active entries, then an ordered pull over IN rows), so column c
+// reproduces the single-column solve with Z_c bit for bit.
+//
+// After either sweep the residual |F_c|_1 of every column is summed in fixed point
+// (exact, order-independent), and a column whose bound |F_c|_1/(1-d) meets the
+// tolerance stops: its entries are no longer touched (Theorem 1 certifies it).
+//
+// Float fluid in the fast sweep picks up a rounding error at every atomic push, so the
+// tile's fluid is recomputed in double from the history, F = F_0 + d P H - H (the fluid
+// of equation HnFn), each time the residual has dropped by REFINE_DROP and before the
+// columns are declared converged.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "batch.h"
 
 namespace di {
 
-struct BatchState {
-    int K = 0;
+constexpr int KMAX = 64;
+constexpr int TILE_THREADS = 256;
+constexpr int TILE_WAVES = TILE_THREADS / WAVE;
+constexpr int TILE_GRID = 2048;   // push / snapshot / pull: grid-stride over rows
+constexpr int REDUCE_TILE_GRID = 1024;
+
+struct TileCtl {
+    long long sweep, budget;
+    int all_done, overflow;
+    u64 tot_nodes, tot_edges;  // rows taken, edge x column pushes
+    double R[KMAX], thr[KMAX], maxF[KMAX];
+    int done[KMAX];
+    long long done_sweep[KMAX];
+    u64 limbsL[KMAX][4];
 };
 
-int init_batch(BatchState *&b, const DevGraph &, SweepParams &, int, const std::vector<i64> &, const double *,
-               hipStream_t) {
-    b = nullptr;
-    set_error("batched solves are not available yet");
-    return DI_EINVAL;
+struct BatchState {
+    int k = 0, fp32 = 0, K = 0, det = 0;
+    i64 n = 0;
+    void *F = nullptr;
+    double *F0 = nullptr;  // (1-d) Z, n x k node-major, double for every fluid type
+    double *H = nullptr;
+    double *snap = nullptr;  // deterministic sweep: pushed value per entry
+    TileCtl *ctl = nullptr, *h_ctl = nullptr;
+    u64 *partR = nullptr;  // [REDUCE_TILE_GRID][KMAX][PSR]
+    u64 *partC = nullptr;  // [TILE_GRID][KMAX][4] leak limbs
+    u64 *partK = nullptr;  // [TILE_GRID][2] rows taken, edge pushes
+    int gridP = 0, gridR = 0;
+    double zsum[KMAX];
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t cap_st = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gexec_spc = 0;
+};
+
+struct TileArgs {
+    const i64 *out_ptr;
+    const int *out_idx;
+    const float *w;
+    const i64 *in_ptr;
+    const int *in_idx;
+    const float *in_w;
+    const double *inv_s;
+    void *F;
+    double *H;
+    double *snap;
+    TileCtl *ctl;
+    u64 *partR, *partC, *partK;
+    i64 n;
+    int k, K;
+    double d;
+};
+
+__device__ __forceinline__ bool tile_limbs_add(Limbs &a, double v, int K) {
+    if (!(v == v) || !(ldexp(v, K) < 0x1p126)) return false;
+    limbs_add(a, v, K);
+    return true;
 }
-int reset_batch(BatchState *, const DevGraph &, const SweepParams &, hipStream_t) { return DI_EINVAL; }
-int diffuse_batch(BatchState *, const DevGraph &, const SweepParams &, const di_opts &, int, int, hipStream_t,
-                  di_stats *) {
-    return DI_EINVAL;
+
+__device__ __forceinline__ bool tile_stopped(const TileCtl *ctl) {
+    return ctl->all_done || ctl->sweep >= ctl->budget;
 }
-int read_batch(BatchState *, const DevGraph &, const SweepParams &, int, void *, int, hipStream_t) { return DI_EINVAL; }
-i64 batch_sweeps(BatchState *, hipStream_t) { return 0; }
+
+// Add per-lane (per-column) values over the waves of the block and store the column
+// sums: out[c * NV + q].  lds: u64[TILE_WAVES * 64 * NV].  Contains barriers.
+template <int NV, unsigned MAXMASK = 0>
+__device__ __forceinline__ void block_columns_store(u64 (&v)[NV], u64 *lds, u64 *out, int k) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lds[(w * WAVE + lane) * NV + q] = v[q];
+    __syncthreads();
+    if (w == 0 && lane < k) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            u64 s = 0;
+            for (int x = 0; x < TILE_WAVES; ++x) {
+                const u64 y = lds[(x * WAVE + lane) * NV + q];
+                s = ((MAXMASK >> q) & 1u) ? (y > s ? y : s) : s + y;
+            }
+            out[lane * NV + q] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Fast sweep (see the file comment).
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
+    __shared__ u64 lds[TILE_WAVES * WAVE * 4];
+    __shared__ u64 kred[2 * TILE_WAVES];
+    const TileCtl *ctl = a.ctl;
+    if (tile_stopped(ctl)) return;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    const bool col = lane < a.k && !ctl->done[lane];
+    const double thr = col ? ctl->thr[lane] : 0.0;
+    T *F = reinterpret_cast<T *>(a.F);
+    Limbs leak;
+    limbs_zero(leak);
+    u64 nodes = 0, edges = 0;
+    int bad = 0;
+    const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
+    for (i64 i = (i64)blockIdx.x * TILE_WAVES + w; i < a.n; i += nwaves) {
+        const i64 slot = i * a.k + lane;
+        const T v = col ? F[slot] : (T)0;
+        if (__ballot(v != (T)0 && fabs((double)v) >= thr) == 0) continue;
+        // take every running column of the row
+        const double f = (double)v;
+        if (v != (T)0) {
+            atomicAdd(&F[slot], -v);
+            a.H[slot] += f;
+        }
+        const i64 b = a.out_ptr[i], e = a.out_ptr[i + 1];
+        nodes += lane == 0 ? 1 : 0;
+        if (e == b) {
+            if (v != (T)0 && !tile_limbs_add(leak, fabs(f), a.K)) bad = 1;
+            continue;
+        }
+        const double q = (a.d * f) * a.inv_s[i];
+        edges += lane == 0 ? (u64)(e - b) * (u64)__popcll(__ballot(v != (T)0)) : 0ull;
+        for (i64 eb = b; eb < e; eb += WAVE) {
+            const int cnt = (int)min((i64)WAVE, e - eb);
+            const int myidx = a.out_idx[eb + min(lane, cnt - 1)];
+            const float myw = WTD ? a.w[eb + min(lane, cnt - 1)] : 1.0f;
+            for (int kk = 0; kk < cnt; ++kk) {
+                const int j = __shfl(myidx, kk, WAVE);
+                const double val = WTD ? q * (double)__shfl(myw, kk, WAVE) : q;
+                if (v != (T)0) atomicAdd(&F[(i64)j * a.k + lane], (T)val);
+            }
+        }
+    }
+    u64 lv[4] = {leak.l[0], leak.l[1], leak.l[2], leak.l[3]};
+    block_columns_store<4>(lv, lds, a.partC + (i64)blockIdx.x * KMAX * 4, a.k);
+    u64 kv[2] = {nodes, edges};
+    block_store_partials<2>(kv, kred, a.partK + (i64)blockIdx.x * 2);
+    if (bad) atomicOr(&a.ctl->overflow, 1);
+}
+
+// Deterministic sweep, step 1: active entries of running columns move to H; snap holds
+// (d f) / s_i for them (0 elsewhere); dangling ones add to the leak.
+template <typename T>
+__global__ void __launch_bounds__(TILE_THREADS) k_tile_snapshot(TileArgs a) {
+    __shared__ u64 lds[TILE_WAVES * WAVE * 4];
+    __shared__ u64 kred[2 * TILE_WAVES];
+    const TileCtl *ctl = a.ctl;
+    if (tile_stopped(ctl)) return;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    const bool col = lane < a.k && !ctl->done[lane];
+    const double thr = col ? ctl->thr[lane] : 0.0;
+    T *F = reinterpret_cast<T *>(a.F);
+    Limbs leak;
+    limbs_zero(leak);
+    u64 nodes = 0, edges = 0;
+    int bad = 0;
+    const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
+    for (i64 i = (i64)blockIdx.x * TILE_WAVES + w; i < a.n; i += nwaves) {
+        const i64 slot = i * a.k + lane;
+        const T v = lane < a.k ? F[slot] : (T)0;
+        const bool act = col && v != (T)0 && fabs((double)v) >= thr;
+        double q = 0.0;
+        if (act) {
+            const double f = (double)v;
+            a.H[slot] += f;
+            F[slot] = (T)0;
+            const double inv = a.inv_s[i];
+            if (inv == 0.0) {
+                if (!tile_limbs_add(leak, fabs(f), a.K)) bad = 1;
+            } else {
+                q = (a.d * f) * inv;
+            }
+        }
+        const u64 am = __ballot(act);
+        if (lane == 0 && am) {
+            nodes += 1;
+            edges += (u64)(a.out_ptr[i + 1] - a.out_ptr[i]) * (u64)__popcll(am);
+        }
+        if (lane < a.k) a.snap[slot] = q;
+    }
+    u64 lv[4] = {leak.l[0], leak.l[1], leak.l[2], leak.l[3]};
+    block_columns_store<4>(lv, lds, a.partC + (i64)blockIdx.x * KMAX * 4, a.k);
+    u64 kv[2] = {nodes, edges};
+    block_store_partials<2>(kv, kred, a.partK + (i64)blockIdx.x * 2);
+    if (bad) atomicOr(&a.ctl->overflow, 1);
+}
+
+// Deterministic sweep, step 2: F_jc = left fold over IN row j (ascending source) of
+// snap_ic (* w), starting from F_jc, in double, rounded once to the fluid type.
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(TILE_THREADS) k_tile_pull(TileArgs a) {
+    const TileCtl *ctl = a.ctl;
+    if (tile_stopped(ctl)) return;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    if (lane >= a.k) return;
+    T *F = reinterpret_cast<T *>(a.F);
+    const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
+    for (i64 j = (i64)blockIdx.x * TILE_WAVES + w; j < a.n; j += nwaves) {
+        const i64 p0 = a.in_ptr[j], p1 = a.in_ptr[j + 1];
+        if (p0 == p1) continue;
+        double acc = (double)F[j * a.k + lane];
+        for (i64 p = p0; p < p1; ++p) {
+            const i64 src = a.in_idx[p];
+            if (WTD) acc += a.snap[src * a.k + lane] * (double)a.in_w[p];
+            else acc += a.snap[src * a.k + lane];
+        }
+        F[j * a.k + lane] = (T)acc;
+    }
+}
+
+// Fluid recomputation: F_jc = (F0_jc + d sum over IN row j of H_ic / s_i (* w)) - H_jc,
+// in double, stored in the fluid type.
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(TILE_THREADS) k_tile_refine(TileArgs a, const double *F0) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    if (lane >= a.k) return;
+    T *F = reinterpret_cast<T *>(a.F);
+    const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
+    for (i64 j = (i64)blockIdx.x * TILE_WAVES + w; j < a.n; j += nwaves) {
+        const i64 p0 = a.in_ptr[j], p1 = a.in_ptr[j + 1];
+        double acc = 0.0;
+        for (i64 p = p0; p < p1; ++p) {
+            const i64 src = a.in_idx[p];
+            const double t = a.H[src * a.k + lane] * a.inv_s[src];
+            acc += WTD ? t * (double)a.in_w[p] : t;
+        }
+        const i64 slot = j * a.k + lane;
+        F[slot] = (T)((F0[slot] + a.d * acc) - a.H[slot]);
+    }
+}
+
+// Per-column fixed-point residual and max |F| into per-workgroup slots.
+template <typename T>
+__global__ void __launch_bounds__(TILE_THREADS) k_tile_reduce(TileArgs a, int force) {
+    __shared__ u64 lds[TILE_WAVES * WAVE * PSR];
+    const TileCtl *ctl = a.ctl;
+    if (!force && tile_stopped(ctl)) return;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    const bool col = lane < a.k;
+    const T *F = reinterpret_cast<const T *>(a.F);
+    Limbs R;
+    limbs_zero(R);
+    u64 mx = 0;
+    int bad = 0;
+    if (col) {
+        const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
+        for (i64 i = (i64)blockIdx.x * TILE_WAVES + w; i < a.n; i += nwaves) {
+            const double v = fabs((double)F[i * a.k + lane]);
+            if (!tile_limbs_add(R, v, a.K)) bad = 1;
+            const u64 bits = (u64)__double_as_longlong(v);
+            mx = bits > mx ? bits : mx;
+        }
+    }
+    u64 v[PSR] = {R.l[0], R.l[1], R.l[2], R.l[3], mx};
+    block_columns_store<PSR, 1u << 4>(v, lds, a.partR + (i64)blockIdx.x * KMAX * PSR, a.k);
+    if (bad) atomicOr(&a.ctl->overflow, 1);
+}
+
+struct TileFin {
+    TileCtl *ctl;
+    const u64 *partR, *partC;
+    int nR, nC;
+    int k, K, mode;  // mode: FIN_DI after a sweep, FIN_INIT for the state at the start of a call
+    double d, theta, tol, n_d;
+};
+
+// One workgroup per column: add the slots, then residual, bound, stop and threshold.
+__global__ void __launch_bounds__(256) k_tile_finalize(TileFin a) {
+    TileCtl *ctl = a.ctl;
+    const int c = blockIdx.x;
+    if (a.mode == FIN_DI && (tile_stopped(ctl) || ctl->done[c])) return;
+    u64 v[PSR + 4];
+#pragma unroll
+    for (int q = 0; q < PSR + 4; ++q) v[q] = 0;
+    for (int b = threadIdx.x; b < a.nR; b += blockDim.x) {
+        const u64 *p = a.partR + ((i64)b * KMAX + c) * PSR;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += p[q];
+        v[4] = p[4] > v[4] ? p[4] : v[4];
+    }
+    for (int b = threadIdx.x; b < a.nC; b += blockDim.x) {
+        const u64 *p = a.partC + ((i64)b * KMAX + c) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[PSR + q] += p[q];
+    }
+    __shared__ u64 lds[(PSR + 4) * 4];
+    __shared__ u64 tot[PSR + 4];
+    block_store_partials<PSR + 4, 1u << 4>(v, lds, tot);
+    if (threadIdx.x != 0) return;
+    const double R = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], a.K);
+    for (int q = 0; q < 4; ++q) ctl->limbsL[c][q] += tot[PSR + q];
+    limbs_normalize(ctl->limbsL[c]);
+    const double mx = __longlong_as_double((long long)tot[4]);
+    ctl->R[c] = R;
+    ctl->maxF[c] = mx;
+    const double bound = R / (1.0 - a.d);
+    if (!(bound == bound)) atomicOr(&ctl->overflow, 1);
+    const int done = bound <= a.tol ? 1 : 0;
+    if (done && !ctl->done[c]) ctl->done_sweep[c] = ctl->sweep + (a.mode == FIN_DI ? 1 : 0);
+    if (!done) ctl->done_sweep[c] = -1;
+    ctl->done[c] = done;
+    double thr = ((a.theta * R) / a.n_d) * (1.0 - 0x1p-30);
+    if (mx < thr) thr = 0.0;  // nothing reaches the threshold: take every nonzero entry
+    ctl->thr[c] = thr;
+}
+
+// Whole-tile control: counters, sweep count, all-done flag.
+__global__ void __launch_bounds__(256) k_tile_control(TileCtl *ctl, const u64 *partK, int nK, int k, int mode) {
+    if (mode == FIN_DI && tile_stopped(ctl)) return;
+    u64 v[2] = {0, 0};
+    if (mode == FIN_DI)
+        for (int b = threadIdx.x; b < nK; b += blockDim.x) {
+            v[0] += partK[2 * b];
+            v[1] += partK[2 * b + 1];
+        }
+    __shared__ u64 lds[2 * 4];
+    __shared__ u64 tot[2];
+    block_store_partials<2>(v, lds, tot);
+    if (threadIdx.x != 0) return;
+    if (mode == FIN_DI) {
+        ctl->tot_nodes += tot[0];
+        ctl->tot_edges += tot[1];
+        ctl->sweep += 1;
+    }
+    int all = 1;
+    for (int c = 0; c < k; ++c) all &= ctl->done[c];
+    ctl->all_done = (all || ctl->overflow) ? 1 : 0;
+}
+
+__global__ void k_tile_begin(TileCtl *ctl, long long max_sweeps) {
+    ctl->overflow = 0;
+    ctl->all_done = 0;
+    ctl->budget = ctl->sweep + max_sweeps;
+}
+
+// node-major tile -> column-major doubles, times an optional per-column scale
+template <typename T>
+__global__ void k_tile_to_colmajor(const T *__restrict__ src, i64 n, int k, const double *__restrict__ scale,
+                                   double *out) {
+    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < n * k; t += (i64)gridDim.x * blockDim.x) {
+        const i64 c = t / n, i = t - c * n;
+        const double v = (double)src[i * k + c];
+        out[t] = scale ? v * scale[c] : v;
+    }
+}
+
+static TileArgs tile_args(BatchState *b, const DevGraph &g, const SweepParams &p) {
+    TileArgs a;
+    a.out_ptr = g.out_ptr;
+    a.out_idx = g.out_idx;
+    a.w = g.w;
+    a.in_ptr = g.in_ptr;
+    a.in_idx = g.in_idx;
+    a.in_w = g.in_w;
+    a.inv_s = g.inv_s;
+    a.F = b->F;
+    a.H = b->H;
+    a.snap = b->snap;
+    a.ctl = b->ctl;
+    a.partR = b->partR;
+    a.partC = b->partC;
+    a.partK = b->partK;
+    a.n = b->n;
+    a.k = b->k;
+    a.K = b->K;
+    a.d = p.d;
+    return a;
+}
+
+static int launch_tile_reduce(BatchState *b, const TileArgs &a, int force, hipStream_t st) {
+    if (b->fp32) k_tile_reduce<float><<<b->gridR, TILE_THREADS, 0, st>>>(a, force);
+    else k_tile_reduce<double><<<b->gridR, TILE_THREADS, 0, st>>>(a, force);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+static int launch_tile_finalize(BatchState *b, const SweepParams &p, int mode, hipStream_t st) {
+    TileFin f;
+    f.ctl = b->ctl;
+    f.partR = b->partR;
+    f.partC = b->partC;
+    f.nR = b->gridR;
+    f.nC = mode == FIN_DI ? b->gridP : 0;
+    f.k = b->k;
+    f.K = b->K;
+    f.mode = mode;
+    f.d = p.d;
+    f.theta = p.theta;
+    f.tol = p.tol;
+    f.n_d = (double)b->n;
+    k_tile_finalize<<<b->k, 256, 0, st>>>(f);
+    DI_LAUNCH_CHECK();
+    k_tile_control<<<1, 256, 0, st>>>(b->ctl, b->partK, b->gridP, b->k, mode);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+static int enqueue_tile_sweep(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
+    const TileArgs a = tile_args(b, g, p);
+    if (b->det) {
+        if (b->fp32) k_tile_snapshot<float><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+        else k_tile_snapshot<double><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+        DI_LAUNCH_CHECK();
+        if (b->fp32) {
+            if (g.weighted) k_tile_pull<float, true><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+            else k_tile_pull<float, false><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+        } else {
+            if (g.weighted) k_tile_pull<double, true><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+            else k_tile_pull<double, false><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+        }
+    } else {
+        if (b->fp32) {
+            if (g.weighted) k_tile_push<float, true><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+            else k_tile_push<float, false><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+        } else {
+            if (g.weighted) k_tile_push<double, true><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+            else k_tile_push<double, false><<<b->gridP, TILE_THREADS, 0, st>>>(a);
+        }
+    }
+    DI_LAUNCH_CHECK();
+    DI_TRY(launch_tile_reduce(b, a, 0, st));
+    return launch_tile_finalize(b, p, FIN_DI, st);
+}
+
+constexpr double REFINE_DROP = 0x1p-14;
+
+// Recompute the fluid (see above), then every column's residual, stop and threshold.
+static int refine_tile(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
+    const TileArgs a = tile_args(b, g, p);
+    if (b->fp32) {
+        if (g.weighted) k_tile_refine<float, true><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0);
+        else k_tile_refine<float, false><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0);
+    } else {
+        if (g.weighted) k_tile_refine<double, true><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0);
+        else k_tile_refine<double, false><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0);
+    }
+    DI_LAUNCH_CHECK();
+    DI_TRY(launch_tile_reduce(b, a, 1, st));
+    return launch_tile_finalize(b, p, FIN_INIT, st);
+}
+
 int batch_K(const BatchState *b) { return b ? b->K : 0; }
-void free_batch(BatchState *b) { delete b; }
+
+void free_batch(BatchState *b) {
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
+    void *ps[] = {b->F, b->F0, b->H, b->snap, b->ctl, b->partR, b->partC, b->partK};
+    for (void *q : ps)
+        if (q) (void)hipFree(q);
+    if (b->h_ctl) (void)hipHostFree(b->h_ctl);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    delete b;
+}
+
+// F_0 = (1-d) Z_c per column, node-major, kept in double (the fluid starts from it
+// rounded to the fluid type); one fixed-point scale for all columns, set by the
+// largest starting entry.  Uploads F_0 and sets b->K, b->zsum.
+static int load_batch_z(BatchState *b, const SweepParams &p, const double *Z) {
+    const i64 n = b->n;
+    const int k = b->k;
+    std::vector<double> f0((size_t)(n * k));
+    double mx = 0.0;
+    for (int c = 0; c < k; ++c) {
+        double zs = 0.0;
+        for (i64 i = 0; i < n; ++i) {
+            const double z = Z ? Z[(i64)c * n + i] : 1.0 / (double)n;
+            zs += z;
+            const double v = (1.0 - p.d) * z;
+            f0[(size_t)(i * k + c)] = v;
+            mx = std::max(mx, std::fabs(p.fp32 ? (double)(float)v : v));
+        }
+        b->zsum[c] = zs;
+    }
+    int e_max = 0;
+    if (mx > 0.0) std::frexp(mx, &e_max);
+    int e_n = 0;
+    while (((i64)1 << e_n) < n) ++e_n;
+    b->K = 118 - (e_max + e_n);
+    DI_HIP(hipMemcpy(b->F0, f0.data(), n * k * 8, hipMemcpyHostToDevice));
+    return DI_OK;
+}
+
+int set_batch_z(BatchState *b, const DevGraph &g, SweepParams &p, const double *Z, hipStream_t st) {
+    DI_TRY(load_batch_z(b, p, Z));
+    p.K = b->K;
+    if (b->gexec) {  // a captured chunk holds the old scale
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    return reset_batch(b, g, p, st);
+}
+
+int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int det, const double *Z,
+               hipStream_t st) {
+    bout = nullptr;
+    if (k < 1 || k > KMAX) {
+        set_error("k must be in 1..%d", KMAX);
+        return DI_EINVAL;
+    }
+    BatchState *b = new (std::nothrow) BatchState();
+    if (!b) {
+        set_error("host allocation failed");
+        return DI_ENOMEM;
+    }
+    const i64 n = g.n;
+    b->k = k;
+    b->n = n;
+    b->fp32 = p.fp32;
+    b->det = det;
+    const size_t T = p.fp32 ? 4 : 8;
+    b->gridP = (int)std::min<i64>(TILE_GRID, (n + TILE_WAVES - 1) / TILE_WAVES);
+    b->gridR = (int)std::min<i64>(REDUCE_TILE_GRID, (n + TILE_WAVES - 1) / TILE_WAVES);
+    auto fail = [&](int code) {
+        free_batch(b);
+        return code;
+    };
+    auto alloc = [&](void **ptr, size_t bytes) -> bool {
+        if (hipMalloc(ptr, bytes) == hipSuccess) return true;
+        set_error("device allocation of %zu bytes failed", bytes);
+        return false;
+    };
+    if (!alloc(&b->F, n * k * T) || !alloc((void **)&b->F0, n * k * 8) || !alloc((void **)&b->H, n * k * 8) ||
+        !alloc((void **)&b->ctl, sizeof(TileCtl)) || !alloc((void **)&b->partR, (size_t)b->gridR * KMAX * PSR * 8) ||
+        !alloc((void **)&b->partC, (size_t)b->gridP * KMAX * 4 * 8) ||
+        !alloc((void **)&b->partK, (size_t)b->gridP * 2 * 8) || (det && !alloc((void **)&b->snap, n * k * 8)))
+        return fail(DI_ENOMEM);
+    if (hipHostMalloc((void **)&b->h_ctl, sizeof(TileCtl), hipHostMallocDefault) != hipSuccess) {
+        set_error("hipHostMalloc failed");
+        return fail(DI_ENOMEM);
+    }
+    if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+        set_error("hipEventCreate failed");
+        return fail(DI_EHIP);
+    }
+    const int zrc = load_batch_z(b, p, Z);
+    if (zrc != DI_OK) return fail(zrc);
+    p.K = b->K;
+    const int rc = reset_batch(b, g, p, st);
+    if (rc != DI_OK) return fail(rc);
+    bout = b;
+    return DI_OK;
+}
+
+int reset_batch(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
+    DI_TRY(launch_init_fluid(b->F0, b->F, b->fp32, b->n * b->k, st));
+    DI_TRY(launch_fill_zero(b->H, b->n * b->k * 8, st));
+    DI_TRY(launch_fill_zero(b->ctl, sizeof(TileCtl), st));
+    DI_TRY(launch_tile_reduce(b, tile_args(b, g, p), 1, st));
+    DI_TRY(launch_tile_finalize(b, p, FIN_INIT, st));
+    DI_HIP(hipStreamSynchronize(st));
+    return DI_OK;
+}
+
+static int sync_tile(BatchState *b, hipStream_t st) {
+    DI_HIP(hipMemcpyAsync(b->h_ctl, b->ctl, sizeof(TileCtl), hipMemcpyDeviceToHost, st));
+    DI_HIP(hipStreamSynchronize(st));
+    return DI_OK;
+}
+
+// spc sweeps, launched directly or through a captured graph (loop_mode = graph)
+static int enqueue_tile_chunk(BatchState *b, const DevGraph &g, const SweepParams &p, int spc, int graph_mode,
+                              hipStream_t st) {
+    if (!graph_mode) {
+        for (int s = 0; s < spc; ++s) DI_TRY(enqueue_tile_sweep(b, g, p, st));
+        return DI_OK;
+    }
+    if (!b->gexec || b->gexec_spc != spc) {
+        if (b->gexec) {
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+        }
+        if (!b->cap_st) DI_HIP(hipStreamCreateWithFlags(&b->cap_st, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        DI_HIP(hipStreamBeginCapture(b->cap_st, hipStreamCaptureModeThreadLocal));
+        int rc = DI_OK;
+        for (int s = 0; s < spc && rc == DI_OK; ++s) rc = enqueue_tile_sweep(b, g, p, b->cap_st);
+        const hipError_t e = hipStreamEndCapture(b->cap_st, &graph);
+        if (rc != DI_OK) return rc;
+        if (e != hipSuccess) {
+            set_error("hipStreamEndCapture: %s", hipGetErrorString(e));
+            return DI_EHIP;
+        }
+        const hipError_t e2 = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) {
+            set_error("hipGraphInstantiate: %s", hipGetErrorString(e2));
+            return DI_EHIP;
+        }
+        b->gexec_spc = spc;
+    }
+    DI_HIP(hipGraphLaunch(b->gexec, st));
+    return DI_OK;
+}
+
+int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const di_opts &o, int spc,
+                  hipStream_t st, di_stats *stats) {
+    if (b->gexec) {  // the tolerance is baked into a captured chunk
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    DI_HIP(hipEventRecord(b->ev0, st));
+    // state of every column under this call's tolerance
+    k_tile_begin<<<1, 1, 0, st>>>(b->ctl, (long long)o.max_sweeps);
+    DI_LAUNCH_CHECK();
+    DI_TRY(launch_tile_reduce(b, tile_args(b, g, p), 1, st));
+    DI_TRY(launch_tile_finalize(b, p, FIN_INIT, st));
+    DI_TRY(sync_tile(b, st));
+    const TileCtl before = *b->h_ctl;
+    auto max_R = [&](const TileCtl &h) {
+        double r = 0.0;
+        for (int c = 0; c < b->k; ++c) r = std::max(r, h.R[c]);
+        return r;
+    };
+    const bool refine = b->fp32 && !b->det;
+    double R_ref = max_R(before);
+    while (!b->h_ctl->all_done) {
+        DI_TRY(enqueue_tile_chunk(b, g, p, spc, o.loop_mode == DI_LOOP_GRAPH, st));
+        DI_TRY(sync_tile(b, st));
+        const TileCtl &h = *b->h_ctl;
+        if (h.overflow) break;
+        if (refine && (h.all_done || max_R(h) <= R_ref * REFINE_DROP)) {
+            DI_TRY(refine_tile(b, g, p, st));
+            DI_TRY(sync_tile(b, st));
+            R_ref = max_R(*b->h_ctl);
+            if (b->h_ctl->all_done || b->h_ctl->overflow) break;
+        } else if (h.all_done) {
+            break;
+        }
+        if (b->h_ctl->sweep >= b->h_ctl->budget) break;
+    }
+    DI_HIP(hipEventRecord(b->ev1, st));
+    DI_TRY(sync_tile(b, st));
+    float ms = 0.0f;
+    DI_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    const TileCtl &h = *b->h_ctl;
+    int all = 1;
+    for (int c = 0; c < b->k; ++c) all &= h.done[c];
+    if (stats) {
+        stats->sweeps = h.sweep - before.sweep;
+        stats->edge_updates = (int64_t)(h.tot_edges - before.tot_edges);
+        stats->node_updates = (int64_t)(h.tot_nodes - before.tot_nodes);
+        double rmax = 0.0, lsum = 0.0, bn = 0.0;
+        for (int c = 0; c < b->k; ++c) {
+            rmax = std::max(rmax, h.R[c]);
+            const double l = limbs_to_double_raw(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
+            lsum += l;
+            bn = std::max(bn, h.R[c] / (1.0 - p.d - p.d * l / b->zsum[c]));
+        }
+        stats->residual = rmax;
+        stats->bound = rmax / (1.0 - p.d);
+        stats->bound_norm = bn;
+        stats->leak = lsum;
+        stats->ms = ms;
+        stats->converged = all && !h.overflow;
+    }
+    if (h.overflow) {
+        set_error("non-finite or out-of-range fluid in the residual");
+        return DI_ENUMERIC;
+    }
+    if (!all) {
+        set_error("sweep budget spent before every column met the tolerance");
+        return DI_ENOCONV;
+    }
+    return DI_OK;
+}
+
+int read_batch(BatchState *b, const DevGraph &g, const SweepParams &p, int what, void *dst, int on_device,
+               hipStream_t st) {
+    (void)g;
+    const i64 n = b->n;
+    const int k = b->k;
+    auto small = [&](const void *src, size_t bytes) -> int {
+        if (on_device) DI_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+        else std::memcpy(dst, src, bytes);
+        return DI_OK;
+    };
+    if (what == DI_RESIDUALS || what == DI_LEAKS || what == DI_DONE_SWEEPS) {
+        DI_TRY(sync_tile(b, st));
+        const TileCtl &h = *b->h_ctl;
+        if (what == DI_DONE_SWEEPS) {
+            std::vector<int64_t> v((size_t)k);
+            for (int c = 0; c < k; ++c) v[c] = h.done[c] ? (int64_t)h.done_sweep[c] : -1;
+            return small(v.data(), sizeof(int64_t) * k);
+        }
+        std::vector<double> v((size_t)k);
+        for (int c = 0; c < k; ++c)
+            v[c] = what == DI_RESIDUALS
+                       ? h.R[c]
+                       : limbs_to_double_raw(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
+        return small(v.data(), sizeof(double) * k);
+    }
+    if (what != DI_X_RAW && what != DI_H && what != DI_F && what != DI_X_NORM) {
+        set_error("read target %d is not available with k > 1", what);
+        return DI_EINVAL;
+    }
+    double *scale = nullptr, *out = (double *)dst;
+    if (what == DI_X_NORM) {  // completion by Z_c / |Z_c|_1 per column (Section 3.3)
+        DI_TRY(sync_tile(b, st));
+        const TileCtl &h = *b->h_ctl;
+        std::vector<double> sc((size_t)k);
+        for (int c = 0; c < k; ++c) {
+            const double l = limbs_to_double_raw(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
+            sc[c] = (1.0 - p.d) / (1.0 - p.d - p.d * l / b->zsum[c]);
+        }
+        DI_HIP(hipMalloc((void **)&scale, sizeof(double) * k));
+        if (hipMemcpy(scale, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(scale);
+            set_error("upload of the completion scales failed");
+            return DI_EHIP;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!on_device) e = hipMalloc((void **)&out, sizeof(double) * std::max<i64>(n * k, 1));
+    if (e == hipSuccess) {
+        const unsigned grid = grid_for(n * k, 256, 16384);
+        if (what == DI_F && b->fp32) k_tile_to_colmajor<float><<<grid, 256, 0, st>>>((const float *)b->F, n, k, nullptr, out);
+        else if (what == DI_F) k_tile_to_colmajor<double><<<grid, 256, 0, st>>>((const double *)b->F, n, k, nullptr, out);
+        else k_tile_to_colmajor<double><<<grid, 256, 0, st>>>(b->H, n, k, scale, out);
+        e = hipGetLastError();
+        if (e == hipSuccess && !on_device) e = hipMemcpyAsync(dst, out, sizeof(double) * n * k, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (!on_device) (void)hipFree(out);
+    }
+    if (scale) (void)hipFree(scale);
+    if (e != hipSuccess) {
+        set_error("batched read failed: %s", hipGetErrorString(e));
+        return DI_EHIP;
+    }
+    return DI_OK;
+}
+
+i64 batch_sweeps(BatchState *b, hipStream_t st) {
+    if (sync_tile(b, st) != DI_OK) return -1;
+    return b->h_ctl->sweep;
+}
 
 }  // namespace di

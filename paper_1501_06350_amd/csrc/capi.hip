@@ -33,7 +33,9 @@ using namespace di;
 
 struct di_ctx {
     DevGraph g;
-    RowBlocks rbin;  // row blocks of IN (power iteration)
+    RowBlocks rbin;  // row blocks of IN (power iteration, fluid recomputation)
+    bool rbin_ready = false;
+    double *ref_ht = nullptr;  // n doubles: H / s for the fluid recomputation
     SolveState s;
     SweepParams p;
     di_opts o{};
@@ -42,11 +44,21 @@ struct di_ctx {
     int k = 1;
     i64 n_graphs = 1;
     std::vector<i64> graph_ptr;
+    // union of graphs: each graph is placed at a range boundary (padding nodes have no
+    // edges and no fluid); internal node gstart[g] + u is node graph_ptr[g] + u
+    i64 n_user = 0;
+    std::vector<i64> gstart;
+    std::vector<int> h_range_graph;
+    i64 *d_gp = nullptr, *d_gs = nullptr;
+    double *d_gscale = nullptr;
+    std::vector<GraphCtl> h_gctl;
+    std::vector<GraphInfo> h_ginfo;
     int rounds = 8;
     int spc = 8;  // sweeps per host check
     double zsum = 1.0;  // sum of Z (single right-hand side)
     bool forward_converged = false;
-    bool pi_ready = false;
+    bool pi_ready = false;  // power-iteration buffers allocated
+    bool pi_done = false;   // X_PI holds the result for the current Z
     DevCtl *h_ctl = nullptr;  // pinned mirror of the control block
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     i64 device_bytes = 0;
@@ -145,19 +157,58 @@ __global__ void k_ctl_begin(DevCtl *c, long long max_sweeps) {
     c->budget = c->sweep + max_sweeps;
 }
 
+int ensure_row_blocks(di_ctx *c) {
+    if (!c->rbin_ready) {
+        DI_TRY(build_row_blocks(c->rbin, c->g.in_ptr, c->g.n, c->st));
+        c->rbin_ready = true;
+    }
+    return DI_OK;
+}
+
+__global__ void k_ctl_reopen(DevCtl *c) { c->done = 0; }
+
+// Control step after a forward step (per graph for a union of graphs).
+int enqueue_finalize(di_ctx *c, int mode, hipStream_t st) {
+    if (c->s.range_graph) return launch_mg_finalize(c->s, c->s.ctl, c->p, mode, c->o.deterministic ? 1 : 0, st);
+    return launch_finalize(c->s.ctl, c->p, mode, st, c->s.partR, c->s.nR, c->s.partC, mode == FIN_INIT ? 0 : c->s.nC);
+}
+
 int reset_state(di_ctx *c) {
     const i64 n = c->g.n;
     const size_t T = c->p.fp32 ? 4 : 8;
-    DI_HIP(hipMemcpyAsync(c->s.F, c->s.F0, n * T, hipMemcpyDeviceToDevice, c->st));
+    DI_TRY(launch_init_fluid(c->s.F0, c->s.F, c->p.fp32, n, c->st));
     DI_TRY(launch_fill_zero(c->s.H, n * 8, c->st));
     DI_TRY(launch_fill_zero(c->s.S[0], n * T, c->st));
     DI_TRY(launch_fill_zero(c->s.S[1], n * T, c->st));
     DI_TRY(launch_fill_zero(c->s.ctl, sizeof(DevCtl), c->st));
+    if (c->s.gctl) DI_TRY(launch_fill_zero(c->s.gctl, sizeof(GraphCtl) * c->s.n_graphs, c->st));
     DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st));
-    DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_INIT, c->st, c->s.partR, c->s.nR, c->s.partC, 0));
+    DI_TRY(enqueue_finalize(c, FIN_INIT, c->st));
     DI_HIP(hipStreamSynchronize(c->st));
     c->forward_converged = false;
     return DI_OK;
+}
+
+// Fluid recomputation (float fluid): deliver the fluid in flight, then F = F_0 + dPH - H
+// in double (equation HnFn), then the residual, threshold and stop state of the result.
+constexpr double REFINE_DROP = 0x1p-14;
+
+int refine_fluid(di_ctx *c) {
+    const size_t T = c->p.fp32 ? 4 : 8;
+    DI_TRY(ensure_row_blocks(c));
+    if (!c->ref_ht) DI_TRY(dalloc(c, &c->ref_ht, c->g.n));
+    DI_TRY(launch_bld_sweep(c->g, c->s, c->p, 0, c->st));
+    DI_TRY(enqueue_finalize(c, FIN_DELIVER, c->st));
+    DI_TRY(launch_fill_zero(c->s.S[0], c->g.n * T, c->st));
+    DI_TRY(launch_fill_zero(c->s.S[1], c->g.n * T, c->st));
+    DI_TRY(launch_refine_fluid(c->g, c->rbin, c->s, c->p, c->ref_ht, c->st));
+    if (!c->s.range_graph) {
+        k_ctl_reopen<<<1, 1, 0, c->st>>>(c->s.ctl);
+        DI_LAUNCH_CHECK();
+    }
+    DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st, 0));
+    DI_TRY(enqueue_finalize(c, FIN_INIT, c->st));
+    return sync_ctl(c, c->s.ctl);
 }
 
 int enqueue_di_sweep(di_ctx *c, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
@@ -165,7 +216,7 @@ int enqueue_di_sweep(di_ctx *c, hipStream_t st, hipEvent_t e0 = nullptr, hipEven
     if (c->o.deterministic) DI_TRY(launch_det_sweep(c->g, c->s, c->p, st));
     else DI_TRY(launch_bld_sweep(c->g, c->s, c->p, c->rounds, st));
     if (e1) DI_HIP(hipEventRecord(e1, st));
-    return launch_finalize(c->s.ctl, c->p, FIN_DI, st, c->s.partR, c->s.nR, c->s.partC, c->s.nC);
+    return enqueue_finalize(c, FIN_DI, st);
 }
 
 int enqueue_pi_iteration(di_ctx *c, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
@@ -241,6 +292,53 @@ void fill_stats(di_stats *st, const DevCtl &h, const DevCtl &before, double d, i
     st->converged = h.done && !h.overflow;
 }
 
+// Internal (padded) layout of a union of graphs -> caller's numbering, times a per-graph
+// scale when given.  Node i of graph g (graph_ptr[g] <= i < graph_ptr[g+1]) sits at
+// gstart[g] + i - graph_ptr[g].
+template <typename T>
+__global__ void k_unpad(const T *__restrict__ src, i64 n_user, const i64 *__restrict__ gp,
+                        const i64 *__restrict__ gs, const double *__restrict__ scale, i64 G, double *dst) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n_user; i += (i64)gridDim.x * blockDim.x) {
+        i64 lo = 0, hi = G - 1;  // last graph with gp[g] <= i
+        while (lo < hi) {
+            const i64 mid = (lo + hi + 1) >> 1;
+            if (gp[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const double v = (double)src[i - gp[lo] + gs[lo]];
+        dst[i] = scale ? v * scale[lo] : v;
+    }
+}
+
+// Per-graph control blocks of a union of graphs, copied to c->h_gctl.
+int sync_gctl(di_ctx *c) {
+    c->h_gctl.resize((size_t)c->s.n_graphs);
+    DI_HIP(hipMemcpyAsync(c->h_gctl.data(), c->s.gctl, sizeof(GraphCtl) * c->s.n_graphs, hipMemcpyDeviceToHost, c->st));
+    DI_HIP(hipStreamSynchronize(c->st));
+    return DI_OK;
+}
+
+// Statistics of a union of graphs: the residual and bounds are the largest over the
+// graphs (each graph is certified on its own), the leak is the sum.
+int fill_stats_mg(di_ctx *c, di_stats *st, const DevCtl &h, const DevCtl &before, float ms) {
+    if (!st) return DI_OK;
+    DI_TRY(sync_gctl(c));
+    fill_stats(st, h, before, c->d, c->p.K, ms, false);
+    double R = 0.0, bn = 0.0, lsum = 0.0;
+    for (i64 g = 0; g < c->s.n_graphs; ++g) {
+        const GraphCtl &gc = c->h_gctl[g];
+        const double l = host_limbs(gc.limbsL, c->p.K);
+        R = std::max(R, gc.R);
+        bn = std::max(bn, gc.R / (1.0 - c->d - c->d * l / c->h_ginfo[g].zsum));
+        lsum += l;
+    }
+    st->residual = R;
+    st->bound = R / (1.0 - c->d);
+    st->bound_norm = bn;
+    st->leak = lsum;
+    return DI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -254,7 +352,8 @@ int di_destroy(di_ctx *c) {
     free_row_blocks(c->rbin);
     void *ps[] = {c->s.F, c->s.F0, c->s.H, c->s.S[0], c->s.S[1], c->s.snap, c->s.frontier, c->s.range_order,
                   c->s.ctl, c->s.X[0], c->s.X[1], c->s.XT[0], c->s.XT[1], c->s.pctl, c->s.Z, c->lam,
-                  c->aF, c->asnap, c->actl, c->s.partR, c->s.partC};
+                  c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.ginfo, c->s.gctl,
+                  c->d_gp, c->d_gs, c->d_gscale, c->ref_ht};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     if (c->b) free_batch(c->b);
@@ -296,7 +395,8 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     if (opt.inner_rounds < 0 || opt.inner_rounds > 64) DI_FAIL(DI_EINVAL, "inner_rounds must be in 0..64");
     if (opt.loop_mode != DI_LOOP_STREAM && opt.loop_mode != DI_LOOP_GRAPH) DI_FAIL(DI_EINVAL, "bad loop_mode");
     if (opt.sweeps_per_sync < 0) DI_FAIL(DI_EINVAL, "sweeps_per_sync must be >= 0");
-    const i64 n = g->n, m = g->m;
+    i64 n = g->n;
+    const i64 m = g->m;
     if (opt.n_graphs > 1) {
         if (opt.graph_ptr[0] != 0 || opt.graph_ptr[opt.n_graphs] != n) DI_FAIL(DI_EINVAL, "graph_ptr must run from 0 to n");
         for (i64 q = 0; q < opt.n_graphs; ++q)
@@ -352,13 +452,68 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         }
     }
 
+    // block-local range size: unweighted graphs use the LDS-resident kernel with 2^11-node
+    // ranges; weighted graphs the largest range whose fluid fits in LDS; small graphs keep
+    // at least ~256 nodes per range so that several workgroups run
+    const int rbmax = opt.fluid_fp32 ? 14 : 13;
+    int rb = opt.range_log2;
+    if (rb == 0) {
+        const int cap = w ? rbmax : 11;
+        rb = 8;
+        while (rb < cap && ((i64)1 << (rb + 1)) * 256 <= n) ++rb;
+    }
+
+    // union of graphs: every graph starts on a range boundary; edges must stay inside
+    // their graph; Z (given, or uniform 1/n_g per graph) is laid out the same way
+    std::vector<i64> pptr, gstart;
+    std::vector<int> pidx;
+    std::vector<double> pz, gzsum;
+    const i64 n_user = n;
+    if (opt.n_graphs > 1) {
+        const i64 G = opt.n_graphs, B = (i64)1 << rb;
+        const i64 *gp = opt.graph_ptr;
+        gstart.resize((size_t)G + 1);
+        gstart[0] = 0;
+        for (i64 q = 0; q < G; ++q) gstart[q + 1] = gstart[q] + ((gp[q + 1] - gp[q] + B - 1) / B) * B;
+        const i64 n2 = gstart[G];
+        if (n2 >= 0x7fffffffll) DI_FAIL(DI_EINVAL, "the graphs padded to ranges of %lld nodes exceed 2^31 - 1 nodes", (long long)B);
+        pptr.assign((size_t)n2 + 1, 0);
+        pidx.resize((size_t)std::max<i64>(m, 1));
+        pz.assign((size_t)n2, 0.0);
+        gzsum.assign((size_t)G, 0.0);
+        for (i64 q = 0; q < G; ++q) {
+            const i64 lo = gp[q], hi = gp[q + 1], ng = hi - lo;
+            for (i64 u = 0; u < gstart[q + 1] - gstart[q]; ++u) pptr[gstart[q] + u] = ptr[lo + std::min(u, ng)];
+            for (i64 e = ptr[lo]; e < ptr[hi]; ++e) {
+                const int t = idx[e];
+                if (t < lo || t >= hi) DI_FAIL(DI_EINVAL, "edge %lld leaves graph %lld (target %d)", (long long)e, (long long)q, t);
+                pidx[e] = (int)(t - lo + gstart[q]);
+            }
+            for (i64 u = 0; u < ng; ++u) {
+                const double z = Z ? Z[lo + u] : 1.0 / (double)ng;
+                pz[gstart[q] + u] = z;
+                gzsum[q] += z;
+            }
+            if (!(gzsum[q] > 0.0)) DI_FAIL(DI_EINVAL, "Z sums to zero on graph %lld", (long long)q);
+        }
+        pptr[n2] = m;
+        n = n2;
+        ptr = pptr.data();
+        idx = pidx.data();
+        Z = pz.data();
+    }
+
     di_ctx *c = new (std::nothrow) di_ctx();
     if (!c) DI_FAIL(DI_ENOMEM, "host allocation failed");
     c->o = opt;
     c->d = d;
     c->k = k;
     c->n_graphs = opt.n_graphs;
-    if (opt.n_graphs > 1) c->graph_ptr.assign(opt.graph_ptr, opt.graph_ptr + opt.n_graphs + 1);
+    c->n_user = n_user;
+    if (opt.n_graphs > 1) {
+        c->graph_ptr.assign(opt.graph_ptr, opt.graph_ptr + opt.n_graphs + 1);
+        c->gstart = gstart;
+    }
     c->st = (hipStream_t)opt.stream;
     c->p.d = d;
     c->p.theta = opt.theta;
@@ -393,16 +548,6 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         return fail(DI_EHIP);
     }
 
-    // block-local range size: unweighted graphs use the LDS-resident kernel with 2^11-node
-    // ranges; weighted graphs the largest range whose fluid fits in LDS; small graphs keep
-    // at least ~256 nodes per range so that several workgroups run
-    int rbmax = c->p.fp32 ? 14 : 13;
-    int rb = opt.range_log2;
-    if (rb == 0) {
-        const int cap = w ? rbmax : 11;
-        rb = 8;
-        while (rb < cap && ((i64)1 << (rb + 1)) * 256 <= n) ++rb;
-    }
     c->rounds = opt.inner_rounds ? opt.inner_rounds : 4;
     c->p.rounds = c->rounds;
     c->spc = opt.sweeps_per_sync ? opt.sweeps_per_sync : 8;
@@ -439,8 +584,8 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     }
 
     // initial fluid F_0 = (1-d) Z, rounded to float in the float-fluid mode; fixed-point scale
-    if (k > 1 || c->n_graphs > 1) {
-        if ((rc = init_batch(c->b, c->g, c->p, k, c->graph_ptr, Z, c->st)) != DI_OK) return fail(rc);
+    if (k > 1) {
+        if ((rc = init_batch(c->b, c->g, c->p, k, opt.deterministic ? 1 : 0, Z, c->st)) != DI_OK) return fail(rc);
         c->p.K = batch_K(c->b);
         *out = c;
         return DI_OK;
@@ -451,25 +596,20 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     c->zsum = 0.0;
     for (i64 i = 0; i < n; ++i) c->zsum += Z ? Z[i] : 1.0 / (double)n;
     c->p.zsum = c->zsum;
+    // F_0 is kept in double; the fluid starts from it rounded to the fluid type
     for (i64 i = 0; i < n; ++i) {
         const double z = Z ? Z[i] : 1.0 / (double)n;
-        double v = (1.0 - d) * z;
-        if (c->p.fp32) v = (double)(float)v;
+        const double v = (1.0 - d) * z;
         f0[i] = v;
-        mx = std::max(mx, std::fabs(v));
+        mx = std::max(mx, std::fabs(c->p.fp32 ? (double)(float)v : v));
     }
     c->p.K = fixed_scale(mx, n);
-    if ((rc = dalloc(c, (char **)&c->s.F, n * T)) || (rc = dalloc(c, (char **)&c->s.F0, n * T)) ||
+    if ((rc = dalloc(c, (char **)&c->s.F, n * T)) || (rc = dalloc(c, &c->s.F0, n)) ||
         (rc = dalloc(c, &c->s.H, n)) || (rc = dalloc(c, (char **)&c->s.S[0], n * T)) ||
         (rc = dalloc(c, (char **)&c->s.S[1], n * T)) || (rc = dalloc(c, &c->s.ctl, 1)))
         return fail(rc);
-    if (c->p.fp32) {
-        std::vector<float> f0f(f0.begin(), f0.end());
-        if (hipMemcpy(c->s.F0, f0f.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess) return fail(DI_EHIP);
-    } else {
-        if (hipMemcpy(c->s.F0, f0.data(), n * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DI_EHIP);
-    }
-    if (Z) {
+    if (hipMemcpy(c->s.F0, f0.data(), n * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DI_EHIP);
+    if (Z && c->n_graphs == 1) {  // power iteration reads Z (one graph only)
         if ((rc = dalloc(c, &c->s.Z, n))) return fail(rc);
         if (hipMemcpy(c->s.Z, Z, n * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DI_EHIP);
     } else {
@@ -477,6 +617,33 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     }
     if (opt.deterministic) {
         if ((rc = dalloc(c, &c->s.snap, n)) || (rc = dalloc(c, &c->s.frontier, n))) return fail(rc);
+    }
+    if (c->n_graphs > 1) {  // per-range graph ids, per-graph constants and control blocks
+        const i64 G = c->n_graphs, nr = c->g.nranges;
+        c->h_range_graph.assign((size_t)nr, 0);
+        c->h_ginfo.resize((size_t)G);
+        for (i64 q = 0; q < G; ++q) {
+            GraphInfo &gi = c->h_ginfo[q];
+            gi.rbeg = c->gstart[q] >> rb;
+            gi.rend = c->gstart[q + 1] >> rb;
+            gi.n_d = (double)(c->graph_ptr[q + 1] - c->graph_ptr[q]);
+            gi.zsum = gzsum[q];
+            for (i64 r = gi.rbeg; r < gi.rend; ++r) c->h_range_graph[r] = (int)q;
+        }
+        std::vector<double> ones((size_t)G, 1.0);
+        if ((rc = dalloc(c, &c->s.range_graph, nr)) || (rc = dalloc(c, &c->s.ginfo, G)) ||
+            (rc = dalloc(c, &c->s.gctl, G)) || (rc = dalloc(c, &c->d_gp, G + 1)) || (rc = dalloc(c, &c->d_gs, G)) ||
+            (rc = dalloc(c, &c->d_gscale, G)))
+            return fail(rc);
+        if (hipMemcpy(c->s.range_graph, c->h_range_graph.data(), sizeof(int) * nr, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->s.ginfo, c->h_ginfo.data(), sizeof(GraphInfo) * G, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->d_gp, c->graph_ptr.data(), sizeof(i64) * (G + 1), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->d_gs, c->gstart.data(), sizeof(i64) * G, hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("upload of the graph table failed");
+            return fail(DI_EHIP);
+        }
+        c->s.n_graphs = G;
+        c->s.rb = rb;
     }
     if ((rc = reset_state(c)) != DI_OK) return fail(rc);
     *out = c;
@@ -489,12 +656,74 @@ int di_reset(di_ctx *c) {
     return reset_state(c);
 }
 
+int di_set_z(di_ctx *c, const double *Z) {
+    if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
+    const i64 nu = c->n_user, n = c->g.n;
+    const int k = c->k;
+    if (Z) {
+        for (int col = 0; col < k; ++col) {
+            double s = 0.0;
+            for (i64 i = 0; i < nu; ++i) {
+                const double v = Z[(i64)col * nu + i];
+                if (!(v >= 0.0) || !std::isfinite(v)) DI_FAIL(DI_EINVAL, "Z[%lld, %d] must be finite and >= 0", (long long)i, col);
+                s += v;
+            }
+            if (!(s > 0.0)) DI_FAIL(DI_EINVAL, "column %d of Z sums to zero", col);
+        }
+    }
+    if (c->b) return set_batch_z(c->b, c->g, c->p, Z, c->st);
+    // layout of the context (padded per graph in a union), F_0 = (1-d) Z in double
+    std::vector<double> f0((size_t)n, 0.0), gz((size_t)c->n_graphs, 0.0);
+    if (c->n_graphs > 1) {
+        for (i64 q = 0; q < c->n_graphs; ++q) {
+            const i64 lo = c->graph_ptr[q], ng = c->graph_ptr[q + 1] - lo;
+            for (i64 u = 0; u < ng; ++u) {
+                const double z = Z ? Z[lo + u] : 1.0 / (double)ng;
+                f0[c->gstart[q] + u] = z;
+                gz[q] += z;
+            }
+            if (!(gz[q] > 0.0)) DI_FAIL(DI_EINVAL, "Z sums to zero on graph %lld", (long long)q);
+        }
+    } else {
+        for (i64 i = 0; i < n; ++i) f0[i] = Z ? Z[i] : 1.0 / (double)n;
+    }
+    double zsum = 0.0, mx = 0.0;
+    for (i64 i = 0; i < n; ++i) {
+        zsum += f0[i];
+        f0[i] = (1.0 - c->d) * f0[i];
+        mx = std::max(mx, std::fabs(c->p.fp32 ? (double)(float)f0[i] : f0[i]));
+    }
+    if (c->n_graphs == 1) {  // power iteration reads Z
+        if (Z) {
+            if (!c->s.Z) DI_TRY(dalloc(c, &c->s.Z, n));
+            DI_HIP(hipMemcpy(c->s.Z, Z, sizeof(double) * n, hipMemcpyHostToDevice));
+        } else if (c->s.Z) {
+            (void)hipFree(c->s.Z);
+            c->s.Z = nullptr;
+        }
+    } else {
+        for (i64 q = 0; q < c->n_graphs; ++q) c->h_ginfo[q].zsum = gz[q];
+        DI_HIP(hipMemcpy(c->s.ginfo, c->h_ginfo.data(), sizeof(GraphInfo) * c->n_graphs, hipMemcpyHostToDevice));
+    }
+    DI_HIP(hipMemcpy(c->s.F0, f0.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    c->zsum = zsum;
+    c->p.zsum = zsum;
+    c->p.K = fixed_scale(mx, n);
+    c->pi_done = false;
+    if (c->gexec) {  // a captured chunk holds the old fixed-point scale
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    return reset_state(c);
+}
+
 int di_diffuse(di_ctx *c, double tol, di_stats *st) {
     if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
     if (!(tol > 0.0) || !std::isfinite(tol)) DI_FAIL(DI_EINVAL, "tol must be finite and > 0");
     c->p.tol = tol;
     if (c->b) {
-        int rc = diffuse_batch(c->b, c->g, c->p, c->o, c->rounds, c->spc, c->st, st);
+        int rc = diffuse_batch(c->b, c->g, c->p, c->o, c->spc, c->st, st);
+        if (rc == DI_OK) c->forward_converged = true;
         return rc;
     }
     if (c->gexec && c->gexec_kind == 0) {  // tolerance is baked into a captured chunk
@@ -502,15 +731,36 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
         c->gexec = nullptr;
     }
     DI_HIP(hipEventRecord(c->ev0, c->st));
-    // recompute the residual of the current state under the new tolerance
-    DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st));
-    DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_INIT, c->st, c->s.partR, c->s.nR, c->s.partC, 0));
-    k_ctl_begin<<<1, 1, 0, c->st>>>(c->s.ctl, (long long)c->o.max_sweeps);
-    DI_LAUNCH_CHECK();
-    DI_TRY(sync_ctl(c, c->s.ctl));
+    const bool mg = c->s.range_graph != nullptr;
+    if (mg) {
+        // every call starts with no fluid in flight (the last one delivered it): clear the
+        // in-flight buffers, then set each graph's state under the new tolerance
+        const size_t T = c->p.fp32 ? 4 : 8;
+        DI_TRY(launch_fill_zero(c->s.S[0], c->g.n * T, c->st));
+        DI_TRY(launch_fill_zero(c->s.S[1], c->g.n * T, c->st));
+        k_ctl_begin<<<1, 1, 0, c->st>>>(c->s.ctl, (long long)c->o.max_sweeps);
+        DI_LAUNCH_CHECK();
+        DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st, 0));
+        DI_TRY(enqueue_finalize(c, FIN_INIT, c->st));
+        DI_TRY(sync_ctl(c, c->s.ctl));
+    } else {
+        // recompute the residual of the current state under the new tolerance
+        DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st));
+        DI_TRY(enqueue_finalize(c, FIN_INIT, c->st));
+        k_ctl_begin<<<1, 1, 0, c->st>>>(c->s.ctl, (long long)c->o.max_sweeps);
+        DI_LAUNCH_CHECK();
+        DI_TRY(sync_ctl(c, c->s.ctl));
+    }
     // FIN_INIT already set done when the tolerance holds; k_ctl_begin cleared it: recheck
     DevCtl before = *c->h_ctl;
-    {
+    if (mg && before.done && !before.overflow) {
+        DI_HIP(hipEventRecord(c->ev1, c->st));
+        DI_HIP(hipEventSynchronize(c->ev1));
+        DI_TRY(fill_stats_mg(c, st, before, before, 0.0f));
+        c->forward_converged = true;
+        return DI_OK;
+    }
+    if (!mg) {
         const double l = host_limbs(before.limbsL, c->p.K);
         const double b = c->p.normalized ? before.R / (1.0 - c->d - c->d * l / c->zsum) : before.R / (1.0 - c->d);
         if (b <= tol) {
@@ -524,24 +774,43 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
     }
     c->kernel_ns = 0.0;
     c->kernel_launches = 0;
+    // Float fluid, block-local sweeps: the fluid is recomputed in double from H whenever
+    // the residual has fallen by REFINE_DROP since the last recomputation, and before the
+    // solve is declared converged, so that the stop rests on the exact residual.
+    const bool refine = c->p.fp32 && !c->o.deterministic;
+    double R_ref = before.R;
+    bool in_flight = true;
     while (true) {
         const long long s0 = c->h_ctl->sweep;
         DI_TRY(enqueue_chunk(c, 0));
         DI_TRY(sync_ctl(c, c->s.ctl));
+        in_flight = true;
         const DevCtl &h = *c->h_ctl;
         if (c->o.timing && c->o.loop_mode == DI_LOOP_STREAM) DI_TRY(collect_timing(c, h.sweep - s0));
-        if (h.done || h.overflow || h.sweep >= h.budget) break;
+        if (h.overflow) break;
+        if (refine && (h.done || h.R <= R_ref * REFINE_DROP)) {
+            DI_TRY(refine_fluid(c));
+            in_flight = false;
+            R_ref = c->h_ctl->R;
+            if (c->h_ctl->done || c->h_ctl->overflow) break;
+        } else if (h.done) {
+            break;
+        }
+        if (c->h_ctl->sweep >= c->h_ctl->budget) break;
     }
-    if (!c->o.deterministic) {  // deliver fluid still in flight so that F is complete
+    // deliver fluid still in flight so that F is complete (in a union of graphs, frozen
+    // graphs have delivered theirs already)
+    if (!c->o.deterministic && in_flight && !(mg && c->h_ctl->done)) {
         DI_TRY(launch_bld_sweep(c->g, c->s, c->p, 0, c->st));
-        DI_TRY(launch_finalize(c->s.ctl, c->p, FIN_DELIVER, c->st, c->s.partR, c->s.nR, c->s.partC, c->s.nC));
+        DI_TRY(enqueue_finalize(c, FIN_DELIVER, c->st));
     }
     DI_HIP(hipEventRecord(c->ev1, c->st));
     DI_TRY(sync_ctl(c, c->s.ctl));
     float ms = 0.0f;
     DI_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     const DevCtl &h = *c->h_ctl;
-    fill_stats(st, h, before, c->d, c->p.K, ms, false, c->zsum);
+    if (mg) DI_TRY(fill_stats_mg(c, st, h, before, ms));
+    else fill_stats(st, h, before, c->d, c->p.K, ms, false, c->zsum);
     if (h.overflow) DI_FAIL(DI_ENUMERIC, "non-finite or out-of-range fluid in the residual");
     if (!h.done) {
         if (st) st->converged = 0;
@@ -558,7 +827,7 @@ int di_power(di_ctx *c, double tol, di_stats *st) {
     const i64 n = c->g.n;
     const size_t T = c->p.fp32 ? 4 : 8;
     if (!c->pi_ready) {
-        DI_TRY(build_row_blocks(c->rbin, c->g.in_ptr, n, c->st));
+        DI_TRY(ensure_row_blocks(c));
         DI_TRY(dalloc(c, &c->s.X[0], n));
         DI_TRY(dalloc(c, &c->s.X[1], n));
         DI_TRY(dalloc(c, (char **)&c->s.XT[0], n * T));
@@ -597,14 +866,90 @@ int di_power(di_ctx *c, double tol, di_stats *st) {
     h.tot_nodes = (u64)(h.sweep * n);
     fill_stats(st, h, before, c->d, c->p.K, ms, true);
     if (h.overflow) DI_FAIL(DI_ENUMERIC, "non-finite value in the power-iteration residual");
+    c->pi_done = true;  // X_PI holds the last iterate (also after DI_ENOCONV)
     if (!h.done) DI_FAIL(DI_ENOCONV, "iteration budget spent before the tolerance");
     return DI_OK;
 }
+
+namespace {
+int copy_small(const void *src, size_t bytes, void *dst, int on_device) {
+    if (on_device) DI_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    else std::memcpy(dst, src, bytes);
+    return DI_OK;
+}
+
+// di_read for a union of graphs: vectors come back in the caller's numbering.
+int read_union(di_ctx *c, int what, void *dst, int on_device) {
+    const i64 G = c->n_graphs, nu = c->n_user;
+    switch (what) {
+    case DI_X_RAW:
+    case DI_H:
+    case DI_X_NORM:
+    case DI_F: {
+        const double *scale = nullptr;
+        if (what == DI_X_NORM) {  // (1-d) / (1-d-d l_g/|Z_g|_1) on graph g (Section 3.3)
+            DI_TRY(sync_gctl(c));
+            std::vector<double> sc((size_t)G);
+            for (i64 q = 0; q < G; ++q)
+                sc[q] = (1.0 - c->d) / (1.0 - c->d - c->d * host_limbs(c->h_gctl[q].limbsL, c->p.K) / c->h_ginfo[q].zsum);
+            DI_HIP(hipMemcpy(c->d_gscale, sc.data(), sizeof(double) * G, hipMemcpyHostToDevice));
+            scale = c->d_gscale;
+        }
+        double *out = (double *)dst;
+        if (!on_device) DI_HIP(hipMalloc((void **)&out, sizeof(double) * nu));
+        const unsigned grid = grid_for(nu, 256, 16384);
+        if (what == DI_F && c->p.fp32)
+            k_unpad<float><<<grid, 256, 0, c->st>>>((const float *)c->s.F, nu, c->d_gp, c->d_gs, nullptr, G, out);
+        else
+            k_unpad<double><<<grid, 256, 0, c->st>>>(what == DI_F ? (const double *)c->s.F : c->s.H, nu, c->d_gp,
+                                                     c->d_gs, scale, G, out);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && !on_device) e = hipMemcpyAsync(dst, out, sizeof(double) * nu, hipMemcpyDeviceToHost, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        if (!on_device) (void)hipFree(out);
+        if (e != hipSuccess) DI_FAIL(DI_EHIP, "read failed: %s", hipGetErrorString(e));
+        return DI_OK;
+    }
+    case DI_RESIDUALS:
+    case DI_LEAKS:
+    case DI_DONE_SWEEPS: {
+        DI_TRY(sync_gctl(c));
+        if (what == DI_DONE_SWEEPS) {
+            std::vector<int64_t> v((size_t)G);
+            for (i64 q = 0; q < G; ++q) v[q] = c->h_gctl[q].state == GS_FROZEN ? c->h_gctl[q].done_sweep : -1;
+            return copy_small(v.data(), sizeof(int64_t) * G, dst, on_device);
+        }
+        std::vector<double> v((size_t)G);
+        for (i64 q = 0; q < G; ++q)
+            v[q] = what == DI_RESIDUALS ? c->h_gctl[q].R : host_limbs(c->h_gctl[q].limbsL, c->p.K);
+        return copy_small(v.data(), sizeof(double) * G, dst, on_device);
+    }
+    case DI_FRONTIER: {
+        if (!c->s.frontier) DI_FAIL(DI_ESTATE, "the frontier is recorded in deterministic mode only");
+        DI_TRY(sync_ctl(c, c->s.ctl));
+        const i64 cnt = (i64)c->h_ctl->fcount_last;
+        std::vector<int> f((size_t)cnt + 2);
+        if (cnt) DI_HIP(hipMemcpy(f.data() + 2, c->s.frontier, sizeof(int) * cnt, hipMemcpyDeviceToHost));
+        for (i64 q = 0; q < cnt; ++q) {
+            const i64 i2 = f[2 + q];
+            const int g = c->h_range_graph[i2 >> c->s.rb];
+            f[2 + q] = (int)(i2 - c->gstart[g] + c->graph_ptr[g]);
+        }
+        std::sort(f.begin() + 2, f.end());
+        std::memcpy(f.data(), &cnt, sizeof(i64));
+        return copy_small(f.data(), sizeof(int) * (cnt + 2), dst, on_device);
+    }
+    default:
+        DI_FAIL(DI_EINVAL, "read target %d is not available for a union of graphs", what);
+    }
+}
+}  // namespace
 
 int di_read(di_ctx *c, int what, void *dst, int on_device) {
     if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
     if (!dst) DI_FAIL(DI_EINVAL, "dst is NULL");
     if (c->b) return read_batch(c->b, c->g, c->p, what, dst, on_device, c->st);
+    if (c->s.range_graph) return read_union(c, what, dst, on_device);
     const i64 n = c->g.n, m = c->g.m;
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     auto copy_out = [&](const void *src, size_t bytes) -> int {
@@ -644,7 +989,7 @@ int di_read(di_ctx *c, int what, void *dst, int on_device) {
         if (!c->lam) DI_FAIL(DI_ESTATE, "no adjoint has been computed");
         return copy_out(c->lam, sizeof(double) * n);
     case DI_X_PI: {
-        if (!c->pi_ready) DI_FAIL(DI_ESTATE, "di_power has not run");
+        if (!c->pi_done) DI_FAIL(DI_ESTATE, "di_power has not run for the current Z");
         DI_TRY(sync_ctl(c, c->s.pctl));
         return copy_out(c->s.X[c->h_ctl->parity], sizeof(double) * n);
     }
@@ -671,9 +1016,12 @@ int di_read(di_ctx *c, int what, void *dst, int on_device) {
     case DI_LEAKS: {
         DI_TRY(sync_ctl(c, c->s.ctl));
         const double v = what == DI_RESIDUALS ? c->h_ctl->R : host_limbs(c->h_ctl->limbsL, c->p.K);
-        if (on_device) DI_HIP(hipMemcpy(dst, &v, sizeof(double), hipMemcpyHostToDevice));
-        else std::memcpy(dst, &v, sizeof(double));
-        return DI_OK;
+        return copy_small(&v, sizeof(double), dst, on_device);
+    }
+    case DI_DONE_SWEEPS: {
+        DI_TRY(sync_ctl(c, c->s.ctl));
+        const int64_t v = c->forward_converged ? (int64_t)c->h_ctl->sweep : -1;
+        return copy_small(&v, sizeof(int64_t), dst, on_device);
     }
     default:
         DI_FAIL(DI_EINVAL, "unknown read target %d", what);
@@ -684,7 +1032,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
     if (!g || !dZ) DI_FAIL(DI_EINVAL, "g and dZ must not be NULL");
     if (!(tol_inf > 0.0) || !std::isfinite(tol_inf)) DI_FAIL(DI_EINVAL, "tol_inf must be finite and > 0");
-    if (c->b) DI_FAIL(DI_EINVAL, "the adjoint supports one right-hand side on one graph");
+    if (c->b || c->n_graphs > 1) DI_FAIL(DI_EINVAL, "the adjoint supports one right-hand side on one graph");
     if (!c->forward_converged) DI_FAIL(DI_ESTATE, "di_adjoint needs a converged di_diffuse first");
     const i64 n = c->g.n;
     if (!c->lam) {
@@ -785,7 +1133,7 @@ struct CkptHeader {
 
 int di_save(di_ctx *c, const char *path) {
     if (!c || !path) DI_FAIL(DI_EINVAL, "NULL argument");
-    if (c->b) DI_FAIL(DI_EINVAL, "checkpoints cover single right-hand-side solves");
+    if (c->b || c->n_graphs > 1) DI_FAIL(DI_EINVAL, "checkpoints cover single right-hand-side solves on one graph");
     const i64 n = c->g.n;
     const size_t T = c->p.fp32 ? 4 : 8;
     DI_TRY(sync_ctl(c, c->s.ctl));
@@ -827,7 +1175,7 @@ __global__ void k_ctl_restore(DevCtl *c, long long sweep, u64 l0, u64 l1, u64 l2
 
 int di_load(di_ctx *c, const char *path) {
     if (!c || !path) DI_FAIL(DI_EINVAL, "NULL argument");
-    if (c->b) DI_FAIL(DI_EINVAL, "checkpoints cover single right-hand-side solves");
+    if (c->b || c->n_graphs > 1) DI_FAIL(DI_EINVAL, "checkpoints cover single right-hand-side solves on one graph");
     const i64 n = c->g.n;
     const size_t T = c->p.fp32 ? 4 : 8;
     FILE *f = std::fopen(path, "rb");
@@ -858,7 +1206,8 @@ int di_load(di_ctx *c, const char *path) {
 int di_info(di_ctx *c, int key, int64_t *value) {
     if (!c || !value) DI_FAIL(DI_EINVAL, "NULL argument");
     switch (key) {
-    case DI_INFO_N: *value = c->g.n; return DI_OK;
+    case DI_INFO_N: *value = c->n_user; return DI_OK;
+    case DI_INFO_N_INTERNAL: *value = c->g.n; return DI_OK;
     case DI_INFO_M: *value = c->g.m; return DI_OK;
     case DI_INFO_K: *value = c->k; return DI_OK;
     case DI_INFO_M_LOCAL: *value = c->g.m_loc; return DI_OK;

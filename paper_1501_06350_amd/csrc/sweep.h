@@ -31,10 +31,31 @@ struct RowBlocks {
 int build_row_blocks(RowBlocks &rb, const i64 *d_ptr, i64 n, hipStream_t st);
 void free_row_blocks(RowBlocks &rb);
 
+// Block-diagonal union of independent graphs (one solve per graph in the same sweeps).
+// Every graph starts on a range boundary, so a range belongs to one graph; per graph
+// the residual, threshold and stop state are kept apart.
+constexpr int GS_ACTIVE = 0;  // sweeping
+constexpr int GS_FINISH = 1;  // certified with fluid in flight: next sweep only delivers it
+constexpr int GS_FROZEN = 2;  // certified, nothing in flight: its ranges are skipped
+
+struct GraphInfo {  // constant per graph
+    i64 rbeg, rend;  // ranges [rbeg, rend)
+    double n_d;      // number of (unpadded) nodes
+    double zsum;     // sum of Z over the graph
+};
+
+struct GraphCtl {  // per-graph control, cleared at reset
+    u64 limbsL[4];
+    double R, thr, maxF;
+    u64 nodes, edges, remote;  // counters of the last step
+    long long done_sweep;      // sweep count when the graph froze
+    int state, guard;
+};
+
 struct SolveState {
     // all pointers device; T = float when fluid_fp32 else double
     void *F = nullptr;       // n fluid
-    void *F0 = nullptr;      // n initial fluid (1-d) Z
+    double *F0 = nullptr;    // n initial fluid (1-d) Z, in double for every fluid type
     double *H = nullptr;     // n history
     void *S[2] = {nullptr, nullptr};  // n fluid in flight to other ranges (parity by ctl->parity)
     double *snap = nullptr;  // n deterministic sweep: pushed value per source
@@ -50,6 +71,12 @@ struct SolveState {
     // per-workgroup partial sums of the last launched step (see PSR / PSC)
     u64 *partR = nullptr, *partC = nullptr;
     i64 nR = 0, nC = 0;
+    // union of graphs (nullptr for one graph)
+    int *range_graph = nullptr;  // nranges: graph of each range
+    GraphInfo *ginfo = nullptr;  // n_graphs
+    GraphCtl *gctl = nullptr;    // n_graphs
+    i64 n_graphs = 0;
+    int rb = 0;
 };
 
 // grid caps of the grid-stride kernels; the partial-sum buffers hold
@@ -76,11 +103,18 @@ int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int
 int set_kernel_attributes();
 int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st, const u64 *partR, i64 nR,
                     const u64 *partC, i64 nC);
-int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st);
+// skip_frozen: in a union of graphs, leave out the graphs that are frozen
+int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st, int skip_frozen = 0);
 int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st);
 int launch_pi_iteration(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, hipStream_t st);
 int launch_pi_init(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st);
+// F = F_0 + d P H - H computed in double over the IN row blocks, stored in the fluid
+// type (ht: n doubles of scratch); no residual
+int launch_refine_fluid(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, double *ht,
+                        hipStream_t st);
 int launch_fill_zero(void *p, i64 bytes, hipStream_t st);
+// F = F0 rounded to the fluid type (count entries)
+int launch_init_fluid(const double *F0, void *F, int fp32, i64 count, hipStream_t st);
 int launch_copy_fluid_to_double(const void *F, int fp32, i64 n, double *dst, hipStream_t st);
 int launch_scaled_copy(const double *H, double scale, i64 n, double *dst, hipStream_t st);
 size_t bld_lds_bytes(int rb, int fp32);
@@ -93,6 +127,9 @@ constexpr int FIN_INIT = 2;   // like FIN_DI but does not count a sweep
 constexpr int FIN_ADJ = 3;    // adjoint: stop on max|F| / (1-d)
 constexpr int FIN_DELIVER = 4;// after delivering fluid in flight: flip parity only
 constexpr int FIN_ADJ_INIT = 5;// FIN_ADJ without counting a sweep
+
+// per-graph control step of a union of graphs (modes FIN_DI, FIN_INIT, FIN_DELIVER)
+int launch_mg_finalize(SolveState &s, DevCtl *ctl, const SweepParams &p, int mode, int det, hipStream_t st);
 
 int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevCtl *ctl, const SweepParams &p,
                      hipStream_t st, u64 *partR, u64 *partC, i64 *nR, i64 *nC);

@@ -16,6 +16,7 @@
 #include "sweep.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 namespace di {
@@ -71,7 +72,21 @@ struct BldArgs {
     int rounds;
     int force;  // run even when the solve is marked done (delivery of fluid in flight)
     u64 *partR, *partC;  // per-workgroup partial sums (one slot per range)
+    const int *range_graph;  // union of graphs: graph of each range (else nullptr)
+    const GraphCtl *gctl;
 };
+
+// Threshold and number of local rounds of range r: the solve's own, or its graph's in a
+// union of graphs.  Returns false when the range's graph is frozen (nothing to do).
+__device__ __forceinline__ bool range_schedule(const int *range_graph, const GraphCtl *gctl, int r, double &thr,
+                                               int &rounds) {
+    if (!range_graph) return true;
+    const GraphCtl &gc = gctl[range_graph[r]];
+    if (gc.state == GS_FROZEN) return false;
+    thr = gc.thr;
+    if (gc.state == GS_FINISH) rounds = 0;
+    return true;
+}
 
 template <typename T, bool WTD>
 __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
@@ -95,8 +110,10 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
     const T *Sprev = reinterpret_cast<const T *>(par ? a.S1 : a.S0);
     T *Snext = reinterpret_cast<T *>(par ? a.S0 : a.S1);
     T *F = reinterpret_cast<T *>(a.F);
-    const double thr = ctl->thr;
+    double thr = ctl->thr;
+    int rounds = a.rounds;
     const int r = a.range_order[blockIdx.x];
+    if (!range_schedule(a.range_graph, a.gctl, r, thr, rounds)) return;
     const i64 base = (i64)r << a.rb;
     const int cnt = (int)min((i64)B, a.n - base);
     if (threadIdx.x == 0) bad = 0;
@@ -147,7 +164,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
     Limbs leak;
     limbs_zero(leak);
     u64 nodes = 0, edges = 0;
-    for (int round = 0; round < a.rounds; ++round) {
+    for (int round = 0; round < rounds; ++round) {
         bool any = false;
         for (int c = my0; c < my1; c += WAVE) {
             const int i = c + lane;
@@ -225,8 +242,8 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
         if (!limbs_add_checked(R, fabs((double)v), a.K)) bad = 1;
         if (s != (T)0 && !limbs_add_checked(R, fabs((double)s) * a.rw[base + i], a.K)) bad = 1;
     }
-    store_residual_partial(R, 0, red, a.partR + (i64)blockIdx.x * PSR);
-    store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)blockIdx.x * PSC);
+    store_residual_partial(R, 0, red, a.partR + (i64)r * PSR);
+    store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)r * PSC);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
 
@@ -255,6 +272,8 @@ static BldArgs make_bld_args(const DevGraph &g, SolveState &s, const SweepParams
     a.force = rounds == 0;
     a.partR = s.partR;
     a.partC = s.partC;
+    a.range_graph = s.range_graph;
+    a.gctl = s.gctl;
     return a;
 }
 
@@ -290,6 +309,8 @@ struct Bld2Args {
     int rounds;
     int force;
     u64 *partR, *partC;
+    const int *range_graph;
+    const GraphCtl *gctl;
 };
 
 // LDS layout of k_bld2_sweep (bytes): F[B], dH[B] (fluid type), deg[B], off[B+1] (u32),
@@ -328,8 +349,10 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     const T *Sprev = reinterpret_cast<const T *>(par ? a.S1 : a.S0);
     T *Snext = reinterpret_cast<T *>(par ? a.S0 : a.S1);
     T *F = reinterpret_cast<T *>(a.F);
-    const double thr = ctl->thr;
+    double thr = ctl->thr;
+    int rounds = a.rounds;
     const int r = a.range_order[blockIdx.x];
+    if (!range_schedule(a.range_graph, a.gctl, r, thr, rounds)) return;
     const i64 base = (i64)r << a.rb;
     const int cnt = (int)min((i64)B, a.n - base);
     const i64 lb = a.loc_base[r];
@@ -419,7 +442,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     Limbs leak;
     limbs_zero(leak);
     u64 nodes = 0, edges = 0;
-    for (int round = 0; round < a.rounds; ++round) {
+    for (int round = 0; round < rounds; ++round) {
         bool any = false;
         for (int c = my0; c < my1; c += WAVE) {
             const int i = c + lane;
@@ -513,8 +536,8 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             }
         }
     }
-    store_residual_partial(R, 0, red, a.partR + (i64)blockIdx.x * PSR);
-    store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)blockIdx.x * PSC);
+    store_residual_partial(R, 0, red, a.partR + (i64)r * PSR);
+    store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)r * PSC);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
 
@@ -561,6 +584,8 @@ int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int
         b.force = rounds == 0;
         b.partR = s.partR;
         b.partC = s.partC;
+        b.range_graph = s.range_graph;
+        b.gctl = s.gctl;
         s.nR = s.nC = g.nranges;
         if (p.fp32) k_bld2_sweep<float><<<(unsigned)g.nranges, thr, lds2, st>>>(b);
         else k_bld2_sweep<double><<<(unsigned)g.nranges, thr, lds2, st>>>(b);
@@ -679,18 +704,187 @@ int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st,
 }
 
 // ---------------------------------------------------------------------------
+// Control step of a union of graphs.  One workgroup per graph adds the slots of the
+// graph's ranges and moves the graph's state:
+//   deterministic sweeps  : certified -> frozen;
+//   block-local sweeps    : certified -> finish (the next sweep of its ranges only
+//                           delivers the fluid in flight), certified after finishing
+//                           -> frozen, else active;
+//   start of a call       : certified -> frozen, else active (nothing is in flight);
+//   delivery at the end   : certified -> frozen.
+// A frozen graph keeps its residual and is left out of every later step of the call.
+// Then one workgroup adds the per-graph counters and sets the solve's done flag.
+// ---------------------------------------------------------------------------
+struct MgFinArgs {
+    DevCtl *ctl;
+    GraphCtl *gctl;
+    const GraphInfo *ginfo;
+    const u64 *partR, *partC;
+    int use_partC;
+    double d, theta, tol;
+    int K, mode, det, normalized;
+};
+
+__global__ void __launch_bounds__(FIN_THREADS) k_mg_finalize(MgFinArgs a) {
+    DevCtl *c = a.ctl;
+    const bool counts = a.mode == FIN_DI;
+    if (counts && (c->done || c->sweep >= c->budget)) return;
+    GraphCtl &gc = a.gctl[blockIdx.x];
+    const GraphInfo gi = a.ginfo[blockIdx.x];
+    const int st0 = gc.state;
+    if (st0 == GS_FROZEN && a.mode != FIN_INIT) {
+        if (threadIdx.x == 0) gc.nodes = gc.edges = gc.remote = 0;
+        return;
+    }
+    u64 v[PSR + PSC];
+#pragma unroll
+    for (int k = 0; k < PSR + PSC; ++k) v[k] = 0;
+    for (i64 r = gi.rbeg + threadIdx.x; r < gi.rend; r += FIN_THREADS) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += a.partR[r * PSR + k];
+        const u64 m = a.partR[r * PSR + 4];
+        v[4] = m > v[4] ? m : v[4];
+        if (a.use_partC) {
+#pragma unroll
+            for (int k = 0; k < PSC; ++k) v[PSR + k] += a.partC[r * PSC + k];
+        }
+    }
+    __shared__ u64 lds[(PSR + PSC) * (FIN_THREADS / WAVE)];
+    __shared__ u64 tot[PSR + PSC];
+    block_store_partials<PSR + PSC, 1u << 4>(v, lds, tot);
+    if (threadIdx.x != 0) return;
+    const double R = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], a.K);
+    for (int k = 0; k < 4; ++k) gc.limbsL[k] += tot[5 + k];
+    limbs_normalize(gc.limbsL);
+    const double l = limbs_to_double_raw(gc.limbsL[0], gc.limbsL[1], gc.limbsL[2], gc.limbsL[3], a.K);
+    const double mx = __longlong_as_double((long long)tot[4]);
+    const u64 nodes = tot[9];
+    gc.nodes = nodes;
+    gc.edges = tot[10];
+    gc.remote = tot[11];
+    gc.R = R;
+    gc.maxF = mx;
+    const double bound = a.normalized ? R / (1.0 - a.d - a.d * l / gi.zsum) : R / (1.0 - a.d);
+    if (!(bound == bound)) atomicOr(&c->overflow, 1);
+    const bool cert = bound <= a.tol;
+    int st = st0;
+    if (a.mode == FIN_DI) {
+        if (a.det) st = cert ? GS_FROZEN : GS_ACTIVE;
+        else st = cert ? (st0 == GS_FINISH ? GS_FROZEN : GS_FINISH) : GS_ACTIVE;
+    } else if (a.mode == FIN_INIT) {
+        st = cert ? GS_FROZEN : GS_ACTIVE;
+    } else {  // FIN_DELIVER
+        st = cert ? GS_FROZEN : GS_ACTIVE;
+    }
+    if (st == GS_FROZEN && st0 != GS_FROZEN) gc.done_sweep = c->sweep + (counts ? 1 : 0);
+    if (a.mode == FIN_INIT && st != GS_FROZEN) gc.done_sweep = -1;
+    gc.state = st;
+    double thr = ((a.theta * R) / gi.n_d) * (1.0 - 0x1p-30);
+    // a block-local sweep that diffused nothing in an active graph (possible only when
+    // theta > 1) is followed by one that takes every node with nonzero fluid
+    if (a.mode == FIN_DI && !a.det && st0 == GS_ACTIVE && nodes == 0) thr = 0.0;
+    gc.guard = mx < thr ? 1 : 0;
+    gc.thr = thr;
+}
+
+__global__ void __launch_bounds__(FIN_THREADS) k_mg_control(DevCtl *c, const GraphCtl *gctl, i64 G, int mode) {
+    const bool counts = mode == FIN_DI;
+    if (counts && (c->done || c->sweep >= c->budget)) return;
+    u64 v[4] = {0, 0, 0, 0};  // nodes, edges, remote deliveries, graphs not frozen
+    for (i64 g = threadIdx.x; g < G; g += FIN_THREADS) {
+        const GraphCtl &gc = gctl[g];
+        v[0] += gc.nodes;
+        v[1] += gc.edges;
+        v[2] += gc.remote;
+        v[3] += gc.state != GS_FROZEN ? 1 : 0;
+    }
+    __shared__ u64 lds[4 * (FIN_THREADS / WAVE)];
+    __shared__ u64 tot[4];
+    block_store_partials<4>(v, lds, tot);
+    if (threadIdx.x != 0) return;
+    // the solve's residual: the largest per-graph residual (each graph has its own bound)
+    double R = 0.0, M = 0.0;
+    for (i64 g = 0; g < G; ++g) {
+        R = gctl[g].R > R ? gctl[g].R : R;
+        M = gctl[g].maxF > M ? gctl[g].maxF : M;
+    }
+    c->R = R;
+    c->maxF = M;
+    if (counts) {
+        c->tot_nodes += tot[0];
+        c->tot_edges += tot[1];
+        c->tot_remote += tot[2];
+        c->sweep += 1;
+        c->parity ^= 1;
+        c->fcount_last = c->fcount;
+    } else if (mode == FIN_DELIVER) {
+        c->tot_edges += tot[1];
+        c->tot_remote += tot[2];
+        c->parity ^= 1;
+    }
+    c->done = (tot[3] == 0 || c->overflow) ? 1 : 0;
+}
+
+int launch_mg_finalize(SolveState &s, DevCtl *ctl, const SweepParams &p, int mode, int det, hipStream_t st) {
+    MgFinArgs a;
+    a.ctl = ctl;
+    a.gctl = s.gctl;
+    a.ginfo = s.ginfo;
+    a.partR = s.partR;
+    a.partC = s.partC;
+    a.use_partC = mode != FIN_INIT;
+    a.d = p.d;
+    a.theta = p.theta;
+    a.tol = p.tol;
+    a.K = p.K;
+    a.mode = mode;
+    a.det = det;
+    a.normalized = p.normalized;
+    k_mg_finalize<<<(unsigned)s.n_graphs, FIN_THREADS, 0, st>>>(a);
+    DI_LAUNCH_CHECK();
+    k_mg_control<<<1, FIN_THREADS, 0, st>>>(ctl, s.gctl, s.n_graphs, mode);
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Residual of F (fixed point) and max |F|: initial state and deterministic sweeps.
 // ---------------------------------------------------------------------------
+// Node loop of a grid-stride kernel, or, for a union of graphs, of the range whose
+// number is the workgroup's (one partial-sum slot per range).
+struct NodeLoop {
+    i64 i0, i1, step;
+};
+
+__device__ __forceinline__ NodeLoop node_loop(i64 n, const int *range_graph, int rb) {
+    NodeLoop L;
+    if (range_graph) {
+        const i64 base = (i64)blockIdx.x << rb;
+        L.i0 = base + threadIdx.x;
+        L.i1 = min(n, base + ((i64)1 << rb));
+        L.step = blockDim.x;
+    } else {
+        L.i0 = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+        L.i1 = n;
+        L.step = (i64)gridDim.x * blockDim.x;
+    }
+    return L;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_reduce_F(const T *__restrict__ F, i64 n, int K, DevCtl *ctl, u64 *partR) {
+__global__ void __launch_bounds__(256) k_reduce_F(const T *__restrict__ F, i64 n, int K, DevCtl *ctl, u64 *partR,
+                                                  const int *range_graph, const GraphCtl *gctl, int rb,
+                                                  int skip_frozen) {
     __shared__ u64 red[PSR * 4];
     __shared__ int bad;
+    if (range_graph && skip_frozen && gctl[range_graph[blockIdx.x]].state == GS_FROZEN) return;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     Limbs R;
     limbs_zero(R);
     u64 mx = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    const NodeLoop L = node_loop(n, range_graph, rb);
+    for (i64 i = L.i0; i < L.i1; i += L.step) {
         const double v = fabs((double)F[i]);
         if (!limbs_add_checked(R, v, K)) bad = 1;
         const u64 b = (u64)__double_as_longlong(v);
@@ -700,10 +894,14 @@ __global__ void __launch_bounds__(256) k_reduce_F(const T *__restrict__ F, i64 n
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
 
-int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st) {
-    const unsigned grid = grid_for(g.n, 256, REDUCE_GRID);
-    if (p.fp32) k_reduce_F<float><<<grid, 256, 0, st>>>((const float *)s.F, g.n, p.K, s.ctl, s.partR);
-    else k_reduce_F<double><<<grid, 256, 0, st>>>((const double *)s.F, g.n, p.K, s.ctl, s.partR);
+int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st, int skip_frozen) {
+    const unsigned grid = s.range_graph ? (unsigned)g.nranges : grid_for(g.n, 256, REDUCE_GRID);
+    if (p.fp32)
+        k_reduce_F<float><<<grid, 256, 0, st>>>((const float *)s.F, g.n, p.K, s.ctl, s.partR, s.range_graph, s.gctl,
+                                                g.rb, skip_frozen);
+    else
+        k_reduce_F<double><<<grid, 256, 0, st>>>((const double *)s.F, g.n, p.K, s.ctl, s.partR, s.range_graph,
+                                                 s.gctl, g.rb, skip_frozen);
     DI_LAUNCH_CHECK();
     s.nR = grid;
     return DI_OK;
@@ -719,15 +917,23 @@ int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipS
 template <typename T>
 __global__ void __launch_bounds__(256) k_det_snapshot(T *F, double *H, double *snap, const double *__restrict__ inv_s,
                                                       const i64 *__restrict__ out_ptr, i64 n, double d, int K,
-                                                      DevCtl *ctl, int *frontier, u64 *partC) {
+                                                      DevCtl *ctl, int *frontier, u64 *partC,
+                                                      const int *range_graph, const GraphCtl *gctl, int rb) {
     __shared__ u64 red[PSC * 4];
     if (ctl->done || ctl->sweep >= ctl->budget) return;
-    const double thr = ctl->thr;
-    const int guard = ctl->guard;
+    double thr = ctl->thr;
+    int guard = ctl->guard;
+    if (range_graph) {
+        const GraphCtl &gc = gctl[range_graph[blockIdx.x]];
+        if (gc.state == GS_FROZEN) return;
+        thr = gc.thr;
+        guard = gc.guard;
+    }
     Limbs leak;
     limbs_zero(leak);
     u64 nodes = 0, edges = 0;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+    const NodeLoop L = node_loop(n, range_graph, rb);
+    for (i64 i = L.i0; i < L.i1; i += L.step) {
         const T v = F[i];
         const bool act = v != (T)0 && (guard || fabs((double)v) >= thr);
         double q = 0.0;
@@ -756,10 +962,12 @@ __global__ void __launch_bounds__(256) k_det_snapshot(T *F, double *H, double *s
 template <typename T, bool WTD>
 __global__ void __launch_bounds__(256) k_det_pull(T *F, const double *__restrict__ snap, const i64 *__restrict__ in_ptr,
                                                   const int *__restrict__ in_idx, const float *__restrict__ in_w, i64 n,
-                                                  DevCtl *ctl) {
+                                                  DevCtl *ctl, const int *range_graph, const GraphCtl *gctl, int rb) {
     if (ctl->done || ctl->sweep >= ctl->budget) return;
     const i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    // rows of a frozen graph: its snapshot values are stale and its fluid stays put
+    if (range_graph && gctl[range_graph[j >> rb]].state == GS_FROZEN) return;
     double acc = (double)F[j];
     const i64 p1 = in_ptr[j + 1];
     for (i64 p = in_ptr[j]; p < p1; ++p) {
@@ -775,23 +983,31 @@ __global__ void k_det_begin(DevCtl *ctl) {
 }
 
 int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hipStream_t st) {
-    const unsigned grid = grid_for(g.n, 256, SNAP_GRID);
+    const unsigned grid = s.range_graph ? (unsigned)g.nranges : grid_for(g.n, 256, SNAP_GRID);
     k_det_begin<<<1, 1, 0, st>>>(s.ctl);
     DI_LAUNCH_CHECK();
-    if (p.fp32) k_det_snapshot<float><<<grid, 256, 0, st>>>((float *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl, s.frontier, s.partC);
-    else k_det_snapshot<double><<<grid, 256, 0, st>>>((double *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl, s.frontier, s.partC);
+    if (p.fp32)
+        k_det_snapshot<float><<<grid, 256, 0, st>>>((float *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K, s.ctl,
+                                                    s.frontier, s.partC, s.range_graph, s.gctl, g.rb);
+    else
+        k_det_snapshot<double><<<grid, 256, 0, st>>>((double *)s.F, s.H, s.snap, g.inv_s, g.out_ptr, g.n, p.d, p.K,
+                                                     s.ctl, s.frontier, s.partC, s.range_graph, s.gctl, g.rb);
     DI_LAUNCH_CHECK();
     const i64 nC = grid;
     const unsigned gridr = grid_for(g.n, 256);
+#define DI_PULL(TT, WW)                                                                                          \
+    k_det_pull<TT, WW><<<gridr, 256, 0, st>>>((TT *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl,          \
+                                              s.range_graph, s.gctl, g.rb)
     if (p.fp32) {
-        if (g.weighted) k_det_pull<float, true><<<gridr, 256, 0, st>>>((float *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
-        else k_det_pull<float, false><<<gridr, 256, 0, st>>>((float *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
+        if (g.weighted) DI_PULL(float, true);
+        else DI_PULL(float, false);
     } else {
-        if (g.weighted) k_det_pull<double, true><<<gridr, 256, 0, st>>>((double *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
-        else k_det_pull<double, false><<<gridr, 256, 0, st>>>((double *)s.F, s.snap, g.in_ptr, g.in_idx, g.in_w, g.n, s.ctl);
+        if (g.weighted) DI_PULL(double, true);
+        else DI_PULL(double, false);
     }
+#undef DI_PULL
     DI_LAUNCH_CHECK();
-    DI_TRY(launch_reduce_F(g, s, p, st));
+    DI_TRY(launch_reduce_F(g, s, p, st, 1));
     s.nC = nC;
     return DI_OK;
 }
@@ -801,6 +1017,11 @@ int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hip
 // xt_j = x_j / s_j prepared by the previous iteration.  One wave per row block:
 // the block's entries are gathered into LDS with coalesced index reads, then each
 // lane folds one row.  Long rows are summed by segments first (k_pi_segments).
+//
+// The same row pull (REF = true) recomputes the fluid from the history, in double:
+// F = F_0 + d P H - H, the fluid that equation HnFn assigns to H.  Float fluid gathers
+// a rounding error at every push; recomputing it restores the identity, so that
+// |F|_1 / (1-d) certifies |x - H|_1 again (Theorem 1).
 // ---------------------------------------------------------------------------
 constexpr int PI_WAVES = 4;
 
@@ -822,14 +1043,20 @@ struct PiArgs {
     i64 n, nrb, nseg;
     int K;
     u64 *partR;
+    // fluid recomputation: ht = H / s (double), F_0, H, the fluid written
+    const double *ht;
+    const double *F0;
+    const double *H;
+    void *Fout;
 };
 
-template <typename T, bool WTD>
+// TX: type of the gathered x / s values; REF: fluid recomputation (always runs)
+template <typename TX, bool WTD, bool REF>
 __global__ void __launch_bounds__(256) k_pi_segments(PiArgs a) {
     __shared__ double red[256 / WAVE];
     DevCtl *ctl = a.ctl;
-    if (ctl->done || ctl->sweep >= ctl->budget) return;
-    const T *xt = reinterpret_cast<const T *>(ctl->parity ? a.XT1 : a.XT0);
+    if (!REF && (ctl->done || ctl->sweep >= ctl->budget)) return;
+    const TX *xt = REF ? reinterpret_cast<const TX *>(a.ht) : reinterpret_cast<const TX *>(ctl->parity ? a.XT1 : a.XT0);
     const i64 sg = blockIdx.x;
     const i64 b = a.seg_b[sg], e = a.seg_e[sg];
     double acc = 0.0;
@@ -857,17 +1084,19 @@ __global__ void __launch_bounds__(256) k_pi_segments(PiArgs a) {
     }
 }
 
-template <typename T, bool WTD>
+// T: type of x / s in power iteration, of the fluid in the recomputation (REF)
+template <typename T, bool WTD, bool REF>
 __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
+    using TX = typename std::conditional<REF, double, T>::type;
     __shared__ double tile[PI_WAVES][RB_NNZ];
     __shared__ u64 red[PSR * PI_WAVES];
     __shared__ int bad;
     DevCtl *ctl = a.ctl;
-    if (ctl->done || ctl->sweep >= ctl->budget) return;
+    if (!REF && (ctl->done || ctl->sweep >= ctl->budget)) return;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
-    const int par = ctl->parity;
-    const T *xt = reinterpret_cast<const T *>(par ? a.XT1 : a.XT0);
+    const int par = REF ? 0 : ctl->parity;
+    const TX *xt = REF ? reinterpret_cast<const TX *>(a.ht) : reinterpret_cast<const TX *>(par ? a.XT1 : a.XT0);
     T *xtn = reinterpret_cast<T *>(par ? a.XT0 : a.XT1);
     const double *x = par ? a.X1 : a.X0;
     double *xn = par ? a.X0 : a.X1;
@@ -934,13 +1163,19 @@ __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
             }
         }
         if (row >= 0) {
-            const double y = a.d * acc + (a.Z ? (1.0 - a.d) * a.Z[row] : a.zc);
-            xn[row] = y;
-            xtn[row] = (T)(y * a.inv_s[row]);
-            if (!limbs_add_checked(R, fabs(y - x[row]), a.K)) bad = 1;
+            if (REF) {
+                const double f = (a.F0[row] + a.d * acc) - a.H[row];
+                reinterpret_cast<T *>(a.Fout)[row] = (T)f;
+            } else {
+                const double y = a.d * acc + (a.Z ? (1.0 - a.d) * a.Z[row] : a.zc);
+                xn[row] = y;
+                xtn[row] = (T)(y * a.inv_s[row]);
+                if (!limbs_add_checked(R, fabs(y - x[row]), a.K)) bad = 1;
+            }
         }
         wave_sync_lds();  // the next item reuses this wave's tile
     }
+    if (REF) return;  // the residual of the recomputed fluid is summed by k_reduce_F
     store_residual_partial(R, 0, red, a.partR + (i64)blockIdx.x * PSR);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
@@ -970,32 +1205,60 @@ static PiArgs make_pi_args(const DevGraph &g, const RowBlocks &rb, SolveState &s
     a.nseg = rb.nseg;
     a.K = p.K;
     a.partR = s.partR;
+    a.ht = nullptr;
+    a.F0 = nullptr;
+    a.H = nullptr;
+    a.Fout = nullptr;
     return a;
 }
 
-int launch_pi_iteration(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, hipStream_t st) {
-    PiArgs a = make_pi_args(g, rb, s, p);
+template <bool REF>
+static int launch_row_pull(PiArgs &a, const DevGraph &g, const RowBlocks &rb, int fp32, hipStream_t st) {
     if (rb.nseg > 0) {
-        if (p.fp32) {
-            if (g.weighted) k_pi_segments<float, true><<<(unsigned)rb.nseg, 256, 0, st>>>(a);
-            else k_pi_segments<float, false><<<(unsigned)rb.nseg, 256, 0, st>>>(a);
+        const unsigned gs = (unsigned)rb.nseg;
+        if (fp32 && !REF) {
+            if (g.weighted) k_pi_segments<float, true, REF><<<gs, 256, 0, st>>>(a);
+            else k_pi_segments<float, false, REF><<<gs, 256, 0, st>>>(a);
         } else {
-            if (g.weighted) k_pi_segments<double, true><<<(unsigned)rb.nseg, 256, 0, st>>>(a);
-            else k_pi_segments<double, false><<<(unsigned)rb.nseg, 256, 0, st>>>(a);
+            if (g.weighted) k_pi_segments<double, true, REF><<<gs, 256, 0, st>>>(a);
+            else k_pi_segments<double, false, REF><<<gs, 256, 0, st>>>(a);
         }
         DI_LAUNCH_CHECK();
     }
     const unsigned grid = grid_for(rb.nrb, PI_WAVES, PI_GRID);
-    s.nR = grid;
-    if (p.fp32) {
-        if (g.weighted) k_pi_rows<float, true><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
-        else k_pi_rows<float, false><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+    if (fp32) {
+        if (g.weighted) k_pi_rows<float, true, REF><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+        else k_pi_rows<float, false, REF><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
     } else {
-        if (g.weighted) k_pi_rows<double, true><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
-        else k_pi_rows<double, false><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+        if (g.weighted) k_pi_rows<double, true, REF><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+        else k_pi_rows<double, false, REF><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
     }
     DI_LAUNCH_CHECK();
     return DI_OK;
+}
+
+int launch_pi_iteration(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, hipStream_t st) {
+    PiArgs a = make_pi_args(g, rb, s, p);
+    s.nR = grid_for(rb.nrb, PI_WAVES, PI_GRID);
+    return launch_row_pull<false>(a, g, rb, p.fp32, st);
+}
+
+__global__ void k_scaled_by_inv_s(const double *__restrict__ H, const double *__restrict__ inv_s, i64 n,
+                                  double *ht) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        ht[i] = H[i] * inv_s[i];
+}
+
+int launch_refine_fluid(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, double *ht,
+                        hipStream_t st) {
+    k_scaled_by_inv_s<<<grid_for(g.n, 256, 16384), 256, 0, st>>>(s.H, g.inv_s, g.n, ht);
+    DI_LAUNCH_CHECK();
+    PiArgs a = make_pi_args(g, rb, s, p);
+    a.ht = ht;
+    a.F0 = s.F0;
+    a.H = s.H;
+    a.Fout = s.F;
+    return launch_row_pull<true>(a, g, rb, p.fp32, st);
 }
 
 __global__ void k_fill_bytes_zero(unsigned *p, i64 words) {
@@ -1006,6 +1269,21 @@ int launch_fill_zero(void *p, i64 bytes, hipStream_t st) {
     const i64 words = (bytes + 3) / 4;
     k_fill_bytes_zero<<<grid_for(words, 256, 8192), 256, 0, st>>>((unsigned *)p, words);
     DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+__global__ void k_round_to_float(const double *__restrict__ src, i64 n, float *dst) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+int launch_init_fluid(const double *F0, void *F, int fp32, i64 count, hipStream_t st) {
+    if (fp32) {
+        k_round_to_float<<<grid_for(count, 256, 16384), 256, 0, st>>>(F0, count, (float *)F);
+        DI_LAUNCH_CHECK();
+    } else {
+        DI_HIP(hipMemcpyAsync(F, F0, sizeof(double) * count, hipMemcpyDeviceToDevice, st));
+    }
     return DI_OK;
 }
 
@@ -1189,7 +1467,7 @@ int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevC
     else k_adj_pull<false><<<grid_for(g.n, 256), 256, 0, st>>>(F, snap, g.out_ptr, g.out_idx, g.w, g.inv_s, g.n, ctl);
     DI_LAUNCH_CHECK();
     const unsigned gr = grid_for(g.n, 256, REDUCE_GRID);
-    k_reduce_F<double><<<gr, 256, 0, st>>>(F, g.n, p.K, ctl, partR);
+    k_reduce_F<double><<<gr, 256, 0, st>>>(F, g.n, p.K, ctl, partR, nullptr, nullptr, 0, 0);
     DI_LAUNCH_CHECK();
     *nR = gr;
     return DI_OK;
@@ -1197,7 +1475,7 @@ int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevC
 
 int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR) {
     const unsigned gr = grid_for(n, 256, REDUCE_GRID);
-    k_reduce_F<double><<<gr, 256, 0, st>>>(F, n, K, ctl, partR);
+    k_reduce_F<double><<<gr, 256, 0, st>>>(F, n, K, ctl, partR, nullptr, nullptr, 0, 0);
     DI_LAUNCH_CHECK();
     *nR = gr;
     return DI_OK;

@@ -38,6 +38,21 @@ def test_status_codes_match_header():
         assert getattr(binding, name) == int(val)
 
 
+def test_read_and_info_keys_match_header():
+    from paper_1501_06350_amd import binding
+    src = open(os.path.join(ROOT, "include", "di.h")).read()
+    found = 0
+    for name, val in re.findall(r"#define DI_(\w+) (\d+)\b", src):
+        if name.startswith("LOOP_"):
+            assert getattr(binding, name) == int(val)
+        elif hasattr(binding, name):
+            assert getattr(binding, name) == int(val), name
+            found += 1
+        elif name.startswith("INFO_"):
+            raise AssertionError("binding lacks %s" % name)
+    assert found >= 28
+
+
 def _csr(n, ptr, idx, w=None):
     from paper_1501_06350_amd import binding
     ptr = np.ascontiguousarray(ptr, dtype=np.int64)
@@ -106,10 +121,48 @@ def test_validation_rejects(lib, case):
     assert len(lib.di_last_error()) > 0
 
 
+@pytest.mark.parametrize("case", ["edge_leaves_graph", "graph_ptr_end", "graph_ptr_flat", "k_with_union",
+                                  "union_zero_Z", "union_no_ptr"])
+def test_union_validation_rejects(lib, case):
+    """A union of graphs (n_graphs > 1) is checked on the host before any device call."""
+    from paper_1501_06350_amd import binding
+    n = 6
+    ptr, idx = [0, 1, 2, 3, 4, 5, 6], [1, 2, 0, 4, 5, 3]  # two 3-cycles
+    gp = [0, 3, 6]
+    Z = None
+    opts = binding.DiOpts()
+    opts.theta = 1.0
+    opts.k = 1
+    if case == "edge_leaves_graph":
+        idx = [1, 2, 3, 4, 5, 3]
+    elif case == "graph_ptr_end":
+        gp = [0, 3, 5]
+    elif case == "graph_ptr_flat":
+        gp = [0, 3, 3, 6]
+    elif case == "k_with_union":
+        opts.k = 2
+    elif case == "union_zero_Z":
+        Z = [0.5, 0.25, 0.25, 0.0, 0.0, 0.0]
+    gpa = np.ascontiguousarray(gp, dtype=np.int64)
+    opts.n_graphs = len(gp) - 1
+    opts.graph_ptr = None if case == "union_no_ptr" else ctypes.c_void_p(gpa.ctypes.data)
+    csr, keep = _csr(n, ptr, idx)
+    rc, ctx = _init(lib, csr, 0.85, Z, opts)
+    assert rc == binding.DI_EINVAL, (case, rc)
+    assert ctx.value is None
+    assert len(lib.di_last_error()) > 0
+
+
 def test_null_arguments(lib):
     from paper_1501_06350_amd import binding
     assert lib.di_init(None, None, 0.85, None, None) == binding.DI_EINVAL
     assert lib.di_diffuse(None, 1e-8, None) == binding.DI_EINVAL
     assert lib.di_power(None, 1e-8, None) == binding.DI_EINVAL
     assert lib.di_read(None, 0, None, 0) == binding.DI_EINVAL
+    assert lib.di_set_z(None, None) == binding.DI_EINVAL
+    assert lib.di_reset(None) == binding.DI_EINVAL
+    assert lib.di_adjoint(None, None, 1e-8, None, None, 0, None) == binding.DI_EINVAL
+    assert lib.di_info(None, 0, None) == binding.DI_EINVAL
+    assert lib.di_save(None, None) == binding.DI_EINVAL
+    assert lib.di_load(None, None) == binding.DI_EINVAL
     assert lib.di_destroy(None) == binding.DI_OK

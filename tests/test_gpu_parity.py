@@ -124,18 +124,19 @@ def test_block_local_solve(gpu, oracle_graphs, name, fp32, rb):
         H = s.read(gpu.H)
         F = s.read(gpu.F)
         assert np.abs(H - x).sum() <= rel * np.abs(x).sum()
-        # certificate (Theorem 1) up to the fluid's rounding
-        assert np.abs(H - x).sum() <= st["bound"] + (rel * np.abs(x).sum() if fp32 else 1e-14)
+        # certificate (Theorem 1); with float fluid the library recomputes F = F_0 + dPH - H
+        # in double before it stops, so only the rounding of that F to float (2^-24) remains
+        assert np.abs(H - x).sum() <= st["bound"] * (1 + 1e-7) + 1e-14
         # mass balance: sum F + (1-d) sum H + d l = (1-d) sum Z
         l = s.read(gpu.LEAKS)[0]
         defect = F.sum() + (1 - D) * H.sum() + D * l - (1 - D) * Z.sum()
         assert abs(defect) <= (1e-6 if fp32 else 1e-13)
-        # invariant H + F = F_0 + d P H (equation HnFn), P applied by the oracle; with float
-        # fluid its L1 defect is the rounding of the float pushes, and it may add at most
-        # defect / (1-d) to |x - H|_1, so it must stay inside the 1e-6 budget
-        F0 = O.initial_fluid(D, Z, fp32)
+        # invariant H + F = F_0 + d P H (equation HnFn) with the exact F_0 = (1-d) Z, P
+        # applied by the oracle; with float fluid its L1 defect is the rounding of the
+        # recomputed fluid to float
+        F0 = O.initial_fluid(D, Z, False)
         if fp32:
-            assert O.invariant_residual_l1(og, D, F0, H, F) <= 1e-6 * (1 - D) * Z.sum()
+            assert O.invariant_residual_l1(og, D, F0, H, F) <= 1e-7 * st["residual"] + 1e-15
         else:
             assert O.invariant_residual(og, D, F0, H, F) <= 1e-15
 
