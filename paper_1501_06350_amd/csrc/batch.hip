@@ -37,6 +37,8 @@ constexpr int TILE_THREADS = 256;
 constexpr int TILE_WAVES = TILE_THREADS / WAVE;
 constexpr int TILE_GRID = 2048;   // push / snapshot / pull: grid-stride over rows
 constexpr int REDUCE_TILE_GRID = 1024;
+constexpr int ROWS_U = 8;  // rows a wave loads before it inspects them (scan and reduce)
+constexpr int EDGES_U = 8; // row gathers in flight per wave in the fluid recomputation
 
 struct TileCtl {
     long long sweep, budget;
@@ -132,33 +134,76 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
     limbs_zero(leak);
     u64 nodes = 0, edges = 0;
     int bad = 0;
-    const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
-    for (i64 i = (i64)blockIdx.x * TILE_WAVES + w; i < a.n; i += nwaves) {
-        const i64 slot = i * a.k + lane;
-        const T v = col ? F[slot] : (T)0;
-        if (__ballot(v != (T)0 && fabs((double)v) >= thr) == 0) continue;
-        // take every running column of the row
-        const double f = (double)v;
-        if (v != (T)0) {
-            atomicAdd(&F[slot], -v);
-            a.H[slot] += f;
+    // Each wave takes ROWS_U consecutive rows at a time.  Every stage issues its loads
+    // for all rows of the batch before it uses any, so that a wave waits for memory
+    // once per stage rather than once per row: (1) the fluid rows, (2) row pointers,
+    // 1/s and history rows of the rows taken, (3) their first 64 out-edges, (4) pushes.
+    // A workgroup owns a contiguous chunk of rows, so that the rows being pushed to at
+    // any moment (mostly in the same host as their source) stay few and cache-resident.
+    const i64 chunk = ((a.n + gridDim.x - 1) / gridDim.x + ROWS_U - 1) / ROWS_U * ROWS_U;
+    const i64 c_end = min(a.n, ((i64)blockIdx.x + 1) * chunk);
+    for (i64 i0 = (i64)blockIdx.x * chunk + (i64)w * ROWS_U; i0 < c_end; i0 += TILE_WAVES * ROWS_U) {
+        T vv[ROWS_U];
+#pragma unroll
+        for (int u = 0; u < ROWS_U; ++u) vv[u] = col ? F[min(i0 + u, a.n - 1) * a.k + lane] : (T)0;
+        unsigned act = 0;  // wave-uniform: bit u = row i0 + u is taken
+#pragma unroll
+        for (int u = 0; u < ROWS_U; ++u)
+            if (i0 + u < a.n && __ballot(vv[u] != (T)0 && fabs((double)vv[u]) >= thr) != 0) act |= 1u << u;
+        if (act == 0) continue;
+        // (2) lanes 0..ROWS_U hold out_ptr[i0 + lane], lanes 0..ROWS_U-1 hold 1/s
+        const i64 myptr = a.out_ptr[min(i0 + (i64)min(lane, ROWS_U), a.n)];
+        const double myinv = a.inv_s[min(i0 + (i64)min(lane, ROWS_U - 1), a.n - 1)];
+        double hv[ROWS_U];
+#pragma unroll
+        for (int u = 0; u < ROWS_U; ++u)
+            hv[u] = ((act >> u) & 1u) && vv[u] != (T)0 ? a.H[(i0 + u) * a.k + lane] : 0.0;
+        i64 bb[ROWS_U];
+        int cnt0[ROWS_U];
+#pragma unroll
+        for (int u = 0; u < ROWS_U; ++u) {
+            bb[u] = __shfl(myptr, u, WAVE);
+            cnt0[u] = (int)min((i64)WAVE, __shfl(myptr, u + 1, WAVE) - bb[u]);
         }
-        const i64 b = a.out_ptr[i], e = a.out_ptr[i + 1];
-        nodes += lane == 0 ? 1 : 0;
-        if (e == b) {
-            if (v != (T)0 && !tile_limbs_add(leak, fabs(f), a.K)) bad = 1;
-            continue;
+        // (3) first chunk of out-edges of every row taken
+        int idx0[ROWS_U];
+        float w0[ROWS_U];
+#pragma unroll
+        for (int u = 0; u < ROWS_U; ++u) {
+            const bool use = ((act >> u) & 1u) && cnt0[u] > 0;
+            const i64 p = bb[u] + min(lane, max(cnt0[u], 1) - 1);
+            idx0[u] = use ? a.out_idx[p] : 0;
+            w0[u] = (WTD && use) ? a.w[p] : 1.0f;
         }
-        const double q = (a.d * f) * a.inv_s[i];
-        edges += lane == 0 ? (u64)(e - b) * (u64)__popcll(__ballot(v != (T)0)) : 0ull;
-        for (i64 eb = b; eb < e; eb += WAVE) {
-            const int cnt = (int)min((i64)WAVE, e - eb);
-            const int myidx = a.out_idx[eb + min(lane, cnt - 1)];
-            const float myw = WTD ? a.w[eb + min(lane, cnt - 1)] : 1.0f;
-            for (int kk = 0; kk < cnt; ++kk) {
-                const int j = __shfl(myidx, kk, WAVE);
-                const double val = WTD ? q * (double)__shfl(myw, kk, WAVE) : q;
-                if (v != (T)0) atomicAdd(&F[(i64)j * a.k + lane], (T)val);
+        // take every running column of the rows (pushes that arrived since the load stay
+        // in F: the taken amount is subtracted), then push
+#pragma unroll
+        for (int u = 0; u < ROWS_U; ++u) {
+            if (!((act >> u) & 1u)) continue;
+            const i64 i = i0 + u;
+            const T v = vv[u];
+            const double f = (double)v;
+            if (v != (T)0) {
+                atomicAdd(&F[i * a.k + lane], -v);
+                a.H[i * a.k + lane] = hv[u] + f;
+            }
+            nodes += lane == 0 ? 1 : 0;
+            const i64 b = bb[u], e = __shfl(myptr, u + 1, WAVE);
+            if (e == b) {
+                if (v != (T)0 && !tile_limbs_add(leak, fabs(f), a.K)) bad = 1;
+                continue;
+            }
+            const double q = (a.d * f) * __shfl(myinv, u, WAVE);
+            edges += lane == 0 ? (u64)(e - b) * (u64)__popcll(__ballot(v != (T)0)) : 0ull;
+            for (i64 eb = b; eb < e; eb += WAVE) {
+                const int cnt = (int)min((i64)WAVE, e - eb);
+                const int myidx = eb == b ? idx0[u] : a.out_idx[eb + min(lane, cnt - 1)];
+                const float myw = eb == b ? w0[u] : (WTD ? a.w[eb + min(lane, cnt - 1)] : 1.0f);
+                for (int kk = 0; kk < cnt; ++kk) {
+                    const int j = __shfl(myidx, kk, WAVE);
+                    const double val = WTD ? q * (double)__shfl(myw, kk, WAVE) : q;
+                    if (v != (T)0) atomicAdd(&F[(i64)j * a.k + lane], (T)val);
+                }
             }
         }
     }
@@ -244,19 +289,37 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_pull(TileArgs a) {
 template <typename T, bool WTD>
 __global__ void __launch_bounds__(TILE_THREADS) k_tile_refine(TileArgs a, const double *F0) {
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
-    if (lane >= a.k) return;
+    const bool col = lane < a.k;  // every lane takes part in the index loads and shuffles
     T *F = reinterpret_cast<T *>(a.F);
     const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
     for (i64 j = (i64)blockIdx.x * TILE_WAVES + w; j < a.n; j += nwaves) {
         const i64 p0 = a.in_ptr[j], p1 = a.in_ptr[j + 1];
         double acc = 0.0;
-        for (i64 p = p0; p < p1; ++p) {
-            const i64 src = a.in_idx[p];
-            const double t = a.H[src * a.k + lane] * a.inv_s[src];
-            acc += WTD ? t * (double)a.in_w[p] : t;
+        // 64 in-edges per step: lane l loads source l's index and scale 1/s (* w); then
+        // EDGES_U history rows are gathered at a time
+        for (i64 pb = p0; pb < p1; pb += WAVE) {
+            const int cnt = (int)min((i64)WAVE, p1 - pb);
+            const int mysrc = a.in_idx[pb + min(lane, cnt - 1)];
+            double mys = a.inv_s[mysrc];
+            if (WTD) mys *= (double)a.in_w[pb + min(lane, cnt - 1)];
+            for (int kb = 0; kb < cnt; kb += EDGES_U) {
+                double hv[EDGES_U], sv[EDGES_U];
+#pragma unroll
+                for (int u = 0; u < EDGES_U; ++u) {
+                    const int kk = min(kb + u, cnt - 1);
+                    const i64 src = __shfl(mysrc, kk, WAVE);
+                    sv[u] = __shfl(mys, kk, WAVE);
+                    hv[u] = col ? a.H[src * a.k + lane] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < EDGES_U; ++u)
+                    if (kb + u < cnt) acc += hv[u] * sv[u];
+            }
         }
-        const i64 slot = j * a.k + lane;
-        F[slot] = (T)((F0[slot] + a.d * acc) - a.H[slot]);
+        if (col) {
+            const i64 slot = j * a.k + lane;
+            F[slot] = (T)((F0[slot] + a.d * acc) - a.H[slot]);
+        }
     }
 }
 
@@ -275,11 +338,18 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_reduce(TileArgs a, int fo
     int bad = 0;
     if (col) {
         const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
-        for (i64 i = (i64)blockIdx.x * TILE_WAVES + w; i < a.n; i += nwaves) {
-            const double v = fabs((double)F[i * a.k + lane]);
-            if (!tile_limbs_add(R, v, a.K)) bad = 1;
-            const u64 bits = (u64)__double_as_longlong(v);
-            mx = bits > mx ? bits : mx;
+        for (i64 i0 = ((i64)blockIdx.x * TILE_WAVES + w) * ROWS_U; i0 < a.n; i0 += nwaves * ROWS_U) {
+            T vv[ROWS_U];
+#pragma unroll
+            for (int u = 0; u < ROWS_U; ++u) vv[u] = F[min(i0 + u, a.n - 1) * a.k + lane];
+#pragma unroll
+            for (int u = 0; u < ROWS_U; ++u) {
+                if (i0 + u >= a.n) break;
+                const double v = fabs((double)vv[u]);
+                if (!tile_limbs_add(R, v, a.K)) bad = 1;
+                const u64 bits = (u64)__double_as_longlong(v);
+                mx = bits > mx ? bits : mx;
+            }
         }
     }
     u64 v[PSR] = {R.l[0], R.l[1], R.l[2], R.l[3], mx};
@@ -454,8 +524,12 @@ static int enqueue_tile_sweep(BatchState *b, const DevGraph &g, const SweepParam
 }
 
 constexpr double REFINE_DROP = 0x1p-14;
+// while the fluid is float, sweeps aim at REFINE_MARGIN * tol so that the residual of
+// the recomputed fluid (the float pushes' rounding added back) still meets tol
+constexpr double REFINE_MARGIN = 0.5;
 
-// Recompute the fluid (see above), then every column's residual, stop and threshold.
+// Recompute the fluid (see above), then every column's residual, stop and threshold
+// under the tolerance in p.
 static int refine_tile(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
     const TileArgs a = tile_args(b, g, p);
     if (b->fp32) {
@@ -646,8 +720,10 @@ int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const 
     };
     const bool refine = b->fp32 && !b->det;
     double R_ref = max_R(before);
+    SweepParams ps = p;  // the sweeps' tolerance
+    if (refine) ps.tol = p.tol * REFINE_MARGIN;
     while (!b->h_ctl->all_done) {
-        DI_TRY(enqueue_tile_chunk(b, g, p, spc, o.loop_mode == DI_LOOP_GRAPH, st));
+        DI_TRY(enqueue_tile_chunk(b, g, ps, spc, o.loop_mode == DI_LOOP_GRAPH, st));
         DI_TRY(sync_tile(b, st));
         const TileCtl &h = *b->h_ctl;
         if (h.overflow) break;

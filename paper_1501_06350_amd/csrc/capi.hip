@@ -192,8 +192,11 @@ int reset_state(di_ctx *c) {
 // Fluid recomputation (float fluid): deliver the fluid in flight, then F = F_0 + dPH - H
 // in double (equation HnFn), then the residual, threshold and stop state of the result.
 constexpr double REFINE_DROP = 0x1p-14;
+// while the fluid is float, sweeps aim at REFINE_MARGIN * tol so that the residual of
+// the recomputed fluid (the float pushes' rounding added back) still meets tol
+constexpr double REFINE_MARGIN = 0.5;
 
-int refine_fluid(di_ctx *c) {
+int refine_fluid(di_ctx *c, double tol) {
     const size_t T = c->p.fp32 ? 4 : 8;
     DI_TRY(ensure_row_blocks(c));
     if (!c->ref_ht) DI_TRY(dalloc(c, &c->ref_ht, c->g.n));
@@ -207,7 +210,11 @@ int refine_fluid(di_ctx *c) {
         DI_LAUNCH_CHECK();
     }
     DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st, 0));
-    DI_TRY(enqueue_finalize(c, FIN_INIT, c->st));
+    const double sweep_tol = c->p.tol;
+    c->p.tol = tol;
+    const int rc = enqueue_finalize(c, FIN_INIT, c->st);
+    c->p.tol = sweep_tol;
+    DI_TRY(rc);
     return sync_ctl(c, c->s.ctl);
 }
 
@@ -780,6 +787,7 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
     const bool refine = c->p.fp32 && !c->o.deterministic;
     double R_ref = before.R;
     bool in_flight = true;
+    if (refine) c->p.tol = tol * REFINE_MARGIN;
     while (true) {
         const long long s0 = c->h_ctl->sweep;
         DI_TRY(enqueue_chunk(c, 0));
@@ -789,7 +797,7 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
         if (c->o.timing && c->o.loop_mode == DI_LOOP_STREAM) DI_TRY(collect_timing(c, h.sweep - s0));
         if (h.overflow) break;
         if (refine && (h.done || h.R <= R_ref * REFINE_DROP)) {
-            DI_TRY(refine_fluid(c));
+            DI_TRY(refine_fluid(c, tol));
             in_flight = false;
             R_ref = c->h_ctl->R;
             if (c->h_ctl->done || c->h_ctl->overflow) break;
@@ -798,6 +806,7 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
         }
         if (c->h_ctl->sweep >= c->h_ctl->budget) break;
     }
+    c->p.tol = tol;
     // deliver fluid still in flight so that F is complete (in a union of graphs, frozen
     // graphs have delivered theirs already)
     if (!c->o.deterministic && in_flight && !(mg && c->h_ctl->done)) {
