@@ -43,11 +43,20 @@ constexpr int EDGES_U = 8; // row gathers in flight per wave in the fluid recomp
 struct TileCtl {
     long long sweep, budget;
     int all_done, overflow;
+    int parity, pad;  // block-local sweeps: which in-flight buffer is read
     u64 tot_nodes, tot_edges;  // rows taken, edge x column pushes
     double R[KMAX], thr[KMAX], maxF[KMAX];
     int done[KMAX];
     long long done_sweep[KMAX];
     u64 limbsL[KMAX][4];
+};
+
+// A delivery unit: cross-range in-entries [e0, e0 + len) (len <= DL_UNIT), sorted by
+// target.  Whole target rows, unless `split`: then the entries are one segment of a
+// row with more than DL_UNIT entries and the sum is added with a device atomic.
+struct DlUnit {
+    i64 e0;
+    int len, split;
 };
 
 struct BatchState {
@@ -67,6 +76,15 @@ struct BatchState {
     hipStream_t cap_st = nullptr;
     hipGraphExec_t gexec = nullptr;
     int gexec_spc = 0;
+    // block-local sweeps
+    int bld = 0, rounds = 4, gridB = 0, gridD = 0;
+    void *S = nullptr;           // in-flight rows (n x k)
+    unsigned char *fl = nullptr; // n: the row of S is nonzero
+    int *blk_ptr = nullptr;      // gridB + 1: each workgroup's share of blk_ranges
+    int *blk_ranges = nullptr;   // nranges: ranges grouped by workgroup
+    DlUnit *units = nullptr;     // delivery units over the cross-range in-entries
+    i64 nunits = 0;
+    int *rem_tgt_abs = nullptr;  // m_rem: absolute target row of each cross-range entry
 };
 
 struct TileArgs {
@@ -99,7 +117,7 @@ __device__ __forceinline__ bool tile_stopped(const TileCtl *ctl) {
 
 // Add per-lane (per-column) values over the waves of the block and store the column
 // sums: out[c * NV + q].  lds: u64[TILE_WAVES * 64 * NV].  Contains barriers.
-template <int NV, unsigned MAXMASK = 0>
+template <int NV, unsigned MAXMASK = 0, int NW = TILE_WAVES>
 __device__ __forceinline__ void block_columns_store(u64 (&v)[NV], u64 *lds, u64 *out, int k) {
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
 #pragma unroll
@@ -109,7 +127,7 @@ __device__ __forceinline__ void block_columns_store(u64 (&v)[NV], u64 *lds, u64 
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             u64 s = 0;
-            for (int x = 0; x < TILE_WAVES; ++x) {
+            for (int x = 0; x < NW; ++x) {
                 const u64 y = lds[(x * WAVE + lane) * NV + q];
                 s = ((MAXMASK >> q) & 1u) ? (y > s ? y : s) : s + y;
             }
@@ -213,6 +231,312 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
     block_store_partials<2>(kv, kred, a.partK + (i64)blockIdx.x * 2);
     if (bad) atomicOr(&a.ctl->overflow, 1);
 }
+
+// ---------------------------------------------------------------------------
+// Block-local fast sweep of the tile, in two kernels per sweep.
+//
+// k_tile_bld: node ids are grouped into ranges of 2^rb rows; a workgroup takes its
+// ranges one after another and keeps a range's fluid tile F[B][k] and the sweep's
+// history increments dH[B][k] (both of the fluid type) in LDS.  For a range it
+//   1. stages the fluid rows (they already hold what other ranges sent last sweep);
+//   2. runs up to `rounds` local rounds: each wave scans its share of rows, takes a row
+//      when some running column reaches its threshold (every running column of the row
+//      is diffused, Section 3.1), adds it to dH and pushes d f P e_i along the row's
+//      local edges with LDS atomics (one k-lane row add per edge);
+//   3. writes F back, adds dH to H, and for rows with cross-range edges writes the
+//      in-flight row S_i = d dH_i / s_i and a flag telling whether it is nonzero.
+// k_tile_deliver: one wave per unit of cross-range in-entries (whole target rows,
+//   or a segment of a long row) gathers the flagged in-flight rows, adds them up per
+//   target in registers and adds the sum to the target's fluid row.
+// No device-scope atomics on the common path: on this chip they are carried out past
+// the per-XCD L2 caches.  The residual of every column, |F|_1 plus the fluid in
+// flight, is summed at write-back; delivery moves fluid without changing it.
+// ---------------------------------------------------------------------------
+// Two workgroups of 8 waves share a compute unit, so that one stages or writes back a
+// range while the other runs local rounds: the range size is the largest whose tiles
+// fit in half of the 160 KB of LDS.
+constexpr int TB_THREADS = 512;
+constexpr int TB_WAVES = TB_THREADS / WAVE;
+constexpr int TB_GRID = 1024;
+constexpr size_t TB_LDS = 78 * 1024;  // fluid tile + dH tile + degrees + local row offsets
+constexpr int DL_THREADS = 256;
+constexpr int DL_WAVES = DL_THREADS / WAVE;
+constexpr int DL_GRID = 4096;
+constexpr int DL_UNIT = 64;  // cross-range entries per delivery unit
+
+struct TileBldArgs {
+    const i64 *loc_ptr;
+    const unsigned short *loc_tgt;
+    const float *loc_w;
+    const i64 *loc_base;
+    const double *rw;
+    const unsigned *deg_flags;
+    const double *inv_s;
+    const int *blk_ptr, *blk_ranges;
+    i64 n, nranges;
+    int rb, k, K, rounds;
+    void *F;
+    double *H;
+    void *S;
+    unsigned char *fl;
+    TileCtl *ctl;
+    double d;
+    u64 *partR, *partC, *partK;
+};
+
+__host__ __device__ inline size_t tile_bld_lds(int rb, int k, int tsize) {
+    const size_t B = (size_t)1 << rb;
+    return 2 * B * k * tsize + B * 4 + (B + 1) * 4;
+}
+
+// dynamic LDS of a launch: the tiles, and at least the per-column reduction scratch
+// that reuses them at the end
+inline size_t tile_bld_lds_launch(int rb, int k, int tsize) {
+    return std::max(tile_bld_lds(rb, k, tsize), (size_t)TB_WAVES * WAVE * PSR * sizeof(u64));
+}
+
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ u64 kred[2 * TB_WAVES];
+    const TileCtl *ctl = a.ctl;
+    if (tile_stopped(ctl)) return;
+    const int B = 1 << a.rb, k = a.k;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    const bool colk = lane < k;
+    const bool col = colk && !ctl->done[lane];
+    const double thr = col ? ctl->thr[lane] : 0.0;
+    T *Fl = reinterpret_cast<T *>(smem);
+    T *Dl = Fl + (size_t)B * k;
+    unsigned *Deg = reinterpret_cast<unsigned *>(Dl + (size_t)B * k);
+    unsigned *Off = Deg + B;
+    T *F = reinterpret_cast<T *>(a.F);
+    T *S = reinterpret_cast<T *>(a.S);
+
+    // residual and leak: each lane (column) adds its values in double; the sums are
+    // raised by 2^-30 relative (far above the rounding of up to 2^22 additions) and
+    // then enter the exact fixed-point sums, so the residual never falls short
+    double Rd = 0.0, Ld = 0.0;
+    u64 mx = 0, nodes = 0, edges = 0;
+    int bad = 0;
+    for (int q = a.blk_ptr[blockIdx.x]; q < a.blk_ptr[blockIdx.x + 1]; ++q) {
+        const int r = a.blk_ranges[q];
+        const i64 base = (i64)r << a.rb;
+        const int cnt = (int)min((i64)B, a.n - base);
+        const i64 lb = a.loc_base[r];
+        // 1. stage: the range's fluid rows are one contiguous block of cnt * k values
+        {
+            constexpr int SU = 8;
+            const int tot = cnt * k;
+            const T *src = F + base * k;
+            for (int e0 = threadIdx.x; e0 < tot; e0 += TB_THREADS * SU) {
+                T v[SU];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) v[u] = src[min(e0 + u * TB_THREADS, tot - 1)];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const int e = e0 + u * TB_THREADS;
+                    if (e < tot) {
+                        Fl[e] = v[u];
+                        Dl[e] = (T)0;
+                    }
+                }
+            }
+            for (int i = threadIdx.x; i <= cnt; i += TB_THREADS) {
+                if (i < cnt) Deg[i] = a.deg_flags[base + i];
+                Off[i] = (unsigned)(a.loc_ptr[base + i] - lb);
+            }
+        }
+        __syncthreads();
+        // 2. local rounds; wave w owns rows [my0, my1)
+        const int sub = (cnt + TB_WAVES - 1) / TB_WAVES;
+        const int my0 = min(cnt, w * sub), my1 = min(cnt, my0 + sub);
+        for (int round = 0; round < a.rounds; ++round) {
+            bool any = false;
+            // rows are scanned RU at a time: their LDS values are read before any is taken
+            constexpr int RU = 4;
+            for (int i0 = my0; i0 < my1; i0 += RU) {
+                T vv[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+                    vv[u] = col && i0 + u < my1
+                                ? __hip_atomic_load(&Fl[(i0 + u) * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                                : (T)0;
+                unsigned act = 0;
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+                    if (__ballot(vv[u] != (T)0 && fabs((double)vv[u]) >= thr) != 0) act |= 1u << u;
+                if (act == 0) continue;
+                any = true;
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    if (!((act >> u) & 1u)) continue;
+                    const int i = i0 + u;
+                    const T v = vv[u];
+                    const double f = col && v != (T)0 ? (double)atomicExch(&Fl[i * k + lane], (T)0) : 0.0;
+                    if (f != 0.0) Dl[i * k + lane] += (T)f;
+                    nodes += lane == 0 ? 1 : 0;
+                    const unsigned deg = Deg[i] & 0x7fffffffu;
+                    if (deg == 0) {
+                        Ld += fabs(f);
+                        continue;
+                    }
+                    const double q = (a.d * f) * (WTD ? a.inv_s[base + i] : 1.0 / (double)deg);
+                    const int st = (int)Off[i], ln = (int)Off[i + 1] - st;
+                    const u64 fm = __ballot(f != 0.0);
+                    edges += lane == 0 ? (u64)ln * (u64)__popcll(fm) : 0ull;
+                    for (int eb = 0; eb < ln; eb += WAVE) {
+                        const int c2 = min(WAVE, ln - eb);
+                        const i64 pe = lb + st + eb + min(lane, c2 - 1);
+                        const int myt = (int)a.loc_tgt[pe];
+                        const float myw = WTD ? a.loc_w[pe] : 1.0f;
+                        for (int kk = 0; kk < c2; ++kk) {
+                            const int t = __builtin_amdgcn_readlane(myt, kk);
+                            const double val =
+                                WTD ? q * (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(myw), kk)) : q;
+                            if (f != 0.0) atomicAdd(&Fl[t * k + lane], (T)val);
+                        }
+                    }
+                }
+            }
+            if (!any) break;
+        }
+        __syncthreads();
+        // 3. write back: a wave takes WU consecutive rows; their history rows (for the
+        // rows with an increment) are all loaded before any is stored
+        constexpr int WU = 4;
+        for (int i0 = w * WU; i0 < cnt; i0 += TB_WAVES * WU) {
+            T vv[WU], dd[WU];
+            double hv[WU], rwv[WU], invv[WU];
+            unsigned df[WU];
+#pragma unroll
+            for (int u = 0; u < WU; ++u) {
+                const int i = min(i0 + u, cnt - 1);
+                vv[u] = colk && i0 + u < cnt ? Fl[i * k + lane] : (T)0;
+                dd[u] = colk && i0 + u < cnt ? Dl[i * k + lane] : (T)0;
+                df[u] = i0 + u < cnt ? Deg[i] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < WU; ++u) {
+                const i64 gi = base + min(i0 + u, cnt - 1);
+                hv[u] = dd[u] != (T)0 ? a.H[gi * k + lane] : 0.0;
+                const bool remote = (df[u] & 0x80000000u) != 0;
+                rwv[u] = remote ? a.rw[gi] : 0.0;
+                invv[u] = remote ? (WTD ? a.inv_s[gi] : 1.0 / (double)(df[u] & 0x7fffffffu)) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < WU; ++u) {
+                if (i0 + u >= cnt) break;
+                const i64 gi = base + i0 + u;
+                const T v = vv[u], dh = dd[u];
+                if (colk) F[gi * k + lane] = v;
+                if (dh != (T)0) a.H[gi * k + lane] = hv[u] + (double)dh;
+                Rd += fabs((double)v);
+                const u64 vb = (u64)__double_as_longlong(fabs((double)v));
+                mx = vb > mx ? vb : mx;
+                if (df[u] & 0x80000000u) {
+                    const T s = dh != (T)0 ? (T)((a.d * (double)dh) * invv[u]) : (T)0;
+                    const bool fl = __ballot(s != (T)0) != 0;
+                    if (fl) {
+                        if (colk) S[gi * k + lane] = s;
+                        if (s != (T)0) Rd += fabs((double)s) * rwv[u];
+                    }
+                    if (lane == 0) a.fl[gi] = fl ? 1 : 0;
+                }
+            }
+        }
+        __syncthreads();  // the next range reuses the LDS tiles
+    }
+    Limbs R, leak;
+    limbs_zero(R);
+    limbs_zero(leak);
+    if (!tile_limbs_add(R, Rd * (1.0 + 0x1p-30), a.K)) bad = 1;
+    if (!tile_limbs_add(leak, Ld, a.K)) bad = 1;
+    // the per-column reductions reuse the tile's LDS (TB_WAVES * 64 * PSR words)
+    u64 *red = reinterpret_cast<u64 *>(smem);
+    u64 rv[PSR] = {R.l[0], R.l[1], R.l[2], R.l[3], mx};
+    block_columns_store<PSR, 1u << 4, TB_WAVES>(rv, red, a.partR + (i64)blockIdx.x * KMAX * PSR, k);
+    u64 lv[4] = {leak.l[0], leak.l[1], leak.l[2], leak.l[3]};
+    block_columns_store<4, 0, TB_WAVES>(lv, red, a.partC + (i64)blockIdx.x * KMAX * 4, k);
+    u64 kv[2] = {nodes, edges};
+    block_store_partials<2>(kv, kred, a.partK + (i64)blockIdx.x * 2);
+    if (bad) atomicOr(&a.ctl->overflow, 1);
+}
+
+struct TileDlArgs {
+    const DlUnit *units;
+    i64 nunits;
+    const int *rem_src;
+    const int *rem_tgt;  // absolute target row of each entry
+    const float *rem_w;
+    const void *S;
+    const unsigned char *fl;
+    void *F;
+    const TileCtl *ctl;
+    int k, force;
+    u64 *partK;  // per-workgroup count of rows delivered
+};
+
+template <typename T, bool WTD>
+__global__ void __launch_bounds__(DL_THREADS) k_tile_deliver(TileDlArgs a) {
+    __shared__ u64 kred[2 * DL_WAVES];
+    if (!a.force && tile_stopped(a.ctl)) return;
+    constexpr int PB = 16;  // in-flight rows gathered per batch
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    const bool colk = lane < a.k;
+    const int k = a.k;
+    const T *S = reinterpret_cast<const T *>(a.S);
+    T *F = reinterpret_cast<T *>(a.F);
+    u64 delivered = 0;
+    const i64 nw = (i64)gridDim.x * DL_WAVES;
+    for (i64 q = (i64)blockIdx.x * DL_WAVES + w; q < a.nunits; q += nw) {
+        const DlUnit un = a.units[q];
+        const i64 p = un.e0 + min(lane, un.len - 1);
+        const int src = a.rem_src[p];
+        const int tgt = a.rem_tgt[p];
+        const float ew = WTD ? a.rem_w[p] : 1.0f;
+        u64 m = __ballot(lane < un.len && a.fl[src] != 0);
+        delivered += lane == 0 ? (u64)__popcll(m) : 0ull;
+        T run = (T)0;
+        while (m) {
+            int bl[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                bl[u] = m ? __ffsll((long long)m) - 1 : -1;
+                m &= m ? m - 1 : 0ull;
+            }
+            T sv[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int s = __builtin_amdgcn_readlane(src, bl[u] < 0 ? bl[0] : bl[u]);
+                const T *row = S + (i64)s * k;
+                sv[u] = colk ? row[lane] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                if (bl[u] < 0) break;
+                const int t = __builtin_amdgcn_readlane(tgt, bl[u]);
+                T val = sv[u];
+                if (WTD)
+                    val = (T)((double)val * (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(ew), bl[u])));
+                run += val;
+                // the run of target t ends at the last flagged entry of the unit, or
+                // where the next flagged entry has another target
+                const int nxt = u + 1 < PB ? bl[u + 1] : (m ? __ffsll((long long)m) - 1 : -1);
+                if (nxt < 0 || __builtin_amdgcn_readlane(tgt, nxt) != t) {
+                    if (colk && run != (T)0) {
+                        if (un.split) atomicAdd(&F[(i64)t * k + lane], run);
+                        else F[(i64)t * k + lane] += run;
+                    }
+                    run = (T)0;
+                }
+            }
+        }
+    }
+    u64 kv[2] = {0, delivered};
+    block_store_partials<2>(kv, kred, a.partK + (i64)blockIdx.x * 2);
+}
+
 
 // Deterministic sweep, step 1: active entries of running columns move to H; snap holds
 // (d f) / s_i for them (0 elsewhere); dangling ones add to the leak.
@@ -368,7 +692,7 @@ struct TileFin {
 // One workgroup per column: add the slots, then residual, bound, stop and threshold.
 __global__ void __launch_bounds__(256) k_tile_finalize(TileFin a) {
     TileCtl *ctl = a.ctl;
-    const int c = blockIdx.x;
+    const int c = blockIdx.x;  // modes FIN_DI (after a sweep), FIN_INIT, FIN_DELIVER
     if (a.mode == FIN_DI && (tile_stopped(ctl) || ctl->done[c])) return;
     u64 v[PSR + 4];
 #pragma unroll
@@ -409,7 +733,7 @@ __global__ void __launch_bounds__(256) k_tile_finalize(TileFin a) {
 __global__ void __launch_bounds__(256) k_tile_control(TileCtl *ctl, const u64 *partK, int nK, int k, int mode) {
     if (mode == FIN_DI && tile_stopped(ctl)) return;
     u64 v[2] = {0, 0};
-    if (mode == FIN_DI)
+    if (mode != FIN_INIT)
         for (int b = threadIdx.x; b < nK; b += blockDim.x) {
             v[0] += partK[2 * b];
             v[1] += partK[2 * b + 1];
@@ -423,6 +747,7 @@ __global__ void __launch_bounds__(256) k_tile_control(TileCtl *ctl, const u64 *p
         ctl->tot_edges += tot[1];
         ctl->sweep += 1;
     }
+    if (mode == FIN_DI || mode == FIN_DELIVER) ctl->parity ^= 1;
     int all = 1;
     for (int c = 0; c < k; ++c) all &= ctl->done[c];
     ctl->all_done = (all || ctl->overflow) ? 1 : 0;
@@ -475,13 +800,15 @@ static int launch_tile_reduce(BatchState *b, const TileArgs &a, int force, hipSt
     return DI_OK;
 }
 
-static int launch_tile_finalize(BatchState *b, const SweepParams &p, int mode, hipStream_t st) {
+// nR / nC / nK: residual, leak and counter slots written by the step just launched
+static int launch_tile_finalize(BatchState *b, const SweepParams &p, int mode, int nR, int nC, int nK,
+                                hipStream_t st) {
     TileFin f;
     f.ctl = b->ctl;
     f.partR = b->partR;
     f.partC = b->partC;
-    f.nR = b->gridR;
-    f.nC = mode == FIN_DI ? b->gridP : 0;
+    f.nR = nR;
+    f.nC = nC;
     f.k = b->k;
     f.K = b->K;
     f.mode = mode;
@@ -491,12 +818,104 @@ static int launch_tile_finalize(BatchState *b, const SweepParams &p, int mode, h
     f.n_d = (double)b->n;
     k_tile_finalize<<<b->k, 256, 0, st>>>(f);
     DI_LAUNCH_CHECK();
-    k_tile_control<<<1, 256, 0, st>>>(b->ctl, b->partK, b->gridP, b->k, mode);
+    k_tile_control<<<1, 256, 0, st>>>(b->ctl, b->partK, nK, b->k, mode);
     DI_LAUNCH_CHECK();
     return DI_OK;
 }
 
+static TileBldArgs tile_bld_args(BatchState *b, const DevGraph &g, const SweepParams &p) {
+    TileBldArgs a;
+    a.loc_ptr = g.loc_ptr;
+    a.loc_tgt = g.loc_tgt;
+    a.loc_w = g.loc_w;
+    a.loc_base = g.loc_base;
+    a.rw = g.rw;
+    a.deg_flags = g.deg_flags;
+    a.inv_s = g.inv_s;
+    a.blk_ptr = b->blk_ptr;
+    a.blk_ranges = b->blk_ranges;
+    a.n = b->n;
+    a.nranges = g.nranges;
+    a.rb = g.rb;
+    a.k = b->k;
+    a.K = b->K;
+    a.rounds = b->rounds;
+    a.F = b->F;
+    a.H = b->H;
+    a.S = b->S;
+    a.fl = b->fl;
+    a.ctl = b->ctl;
+    a.d = p.d;
+    a.partR = b->partR;
+    a.partC = b->partC;
+    a.partK = b->partK;
+    return a;
+}
+
+// counters of the delivery go to partK slots gridB .. gridB + gridD - 1
+static int launch_tile_deliver(BatchState *b, const DevGraph &g, hipStream_t st) {
+    if (b->nunits == 0) return DI_OK;
+    TileDlArgs a;
+    a.units = b->units;
+    a.nunits = b->nunits;
+    a.rem_src = g.rem_src;
+    a.rem_tgt = b->rem_tgt_abs;
+    a.rem_w = g.rem_w;
+    a.S = b->S;
+    a.fl = b->fl;
+    a.F = b->F;
+    a.ctl = b->ctl;
+    a.k = b->k;
+    a.force = 0;
+    a.partK = b->partK + (size_t)b->gridB * 2;
+    if (b->fp32) {
+        if (g.weighted) k_tile_deliver<float, true><<<b->gridD, DL_THREADS, 0, st>>>(a);
+        else k_tile_deliver<float, false><<<b->gridD, DL_THREADS, 0, st>>>(a);
+    } else {
+        if (g.weighted) k_tile_deliver<double, true><<<b->gridD, DL_THREADS, 0, st>>>(a);
+        else k_tile_deliver<double, false><<<b->gridD, DL_THREADS, 0, st>>>(a);
+    }
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+static int launch_tile_bld(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
+    const TileBldArgs a = tile_bld_args(b, g, p);
+    const size_t lds = tile_bld_lds_launch(g.rb, b->k, b->fp32 ? 4 : 8);
+    if (b->fp32) {
+        if (g.weighted) k_tile_bld<float, true><<<b->gridB, TB_THREADS, lds, st>>>(a);
+        else k_tile_bld<float, false><<<b->gridB, TB_THREADS, lds, st>>>(a);
+    } else {
+        if (g.weighted) k_tile_bld<double, true><<<b->gridB, TB_THREADS, lds, st>>>(a);
+        else k_tile_bld<double, false><<<b->gridB, TB_THREADS, lds, st>>>(a);
+    }
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+int tile_range_log2(int k, int fp32) {
+    for (int rb = 11; rb >= 6; --rb)
+        if (tile_bld_lds(rb, k, fp32 ? 4 : 8) <= TB_LDS) return rb;
+    return 0;
+}
+
+static int set_tile_attributes() {
+    static bool done = false;
+    if (done) return DI_OK;
+    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS));
+    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS));
+    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS));
+    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS));
+    done = true;
+    return DI_OK;
+}
+
 static int enqueue_tile_sweep(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
+    if (b->bld) {  // every sweep ends with its fluid delivered: nothing in flight between sweeps
+        DI_TRY(launch_tile_bld(b, g, p, st));
+        DI_TRY(launch_tile_deliver(b, g, st));
+        return launch_tile_finalize(b, p, FIN_DI, b->gridB, b->gridB, b->gridB + b->gridD, st);
+    }
     const TileArgs a = tile_args(b, g, p);
     if (b->det) {
         if (b->fp32) k_tile_snapshot<float><<<b->gridP, TILE_THREADS, 0, st>>>(a);
@@ -520,7 +939,7 @@ static int enqueue_tile_sweep(BatchState *b, const DevGraph &g, const SweepParam
     }
     DI_LAUNCH_CHECK();
     DI_TRY(launch_tile_reduce(b, a, 0, st));
-    return launch_tile_finalize(b, p, FIN_DI, st);
+    return launch_tile_finalize(b, p, FIN_DI, b->gridR, b->gridP, b->gridP, st);
 }
 
 constexpr double REFINE_DROP = 0x1p-14;
@@ -541,7 +960,7 @@ static int refine_tile(BatchState *b, const DevGraph &g, const SweepParams &p, h
     }
     DI_LAUNCH_CHECK();
     DI_TRY(launch_tile_reduce(b, a, 1, st));
-    return launch_tile_finalize(b, p, FIN_INIT, st);
+    return launch_tile_finalize(b, p, FIN_INIT, b->gridR, 0, 0, st);
 }
 
 int batch_K(const BatchState *b) { return b ? b->K : 0; }
@@ -550,7 +969,9 @@ void free_batch(BatchState *b) {
     if (!b) return;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
-    void *ps[] = {b->F, b->F0, b->H, b->snap, b->ctl, b->partR, b->partC, b->partK};
+    void *ps[] = {b->F,   b->F0,      b->H,         b->snap,  b->ctl,         b->partR,
+                  b->partC, b->partK, b->S,       b->fl,        b->blk_ptr, b->blk_ranges,
+                  b->units, b->rem_tgt_abs};
     for (void *q : ps)
         if (q) (void)hipFree(q);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
@@ -597,8 +1018,95 @@ int set_batch_z(BatchState *b, const DevGraph &g, SweepParams &p, const double *
     return reset_batch(b, g, p, st);
 }
 
+// Longest-processing-time assignment of ranges to the block-local workgroups; a range's
+// work is its cross-range entries, local edges and rows.
+static int assign_ranges(BatchState *b, const DevGraph &g) {
+    const i64 nr = g.nranges;
+    std::vector<i64> rbase(nr + 1), lbase(nr + 1);
+    DI_HIP(hipMemcpy(rbase.data(), g.rem_base, sizeof(i64) * (nr + 1), hipMemcpyDeviceToHost));
+    DI_HIP(hipMemcpy(lbase.data(), g.loc_base, sizeof(i64) * (nr + 1), hipMemcpyDeviceToHost));
+    std::vector<i64> work((size_t)nr);
+    for (i64 r = 0; r < nr; ++r) {
+        const i64 rows = std::min<i64>((i64)1 << g.rb, g.n - (r << g.rb));
+        work[r] = (rbase[r + 1] - rbase[r]) + (lbase[r + 1] - lbase[r]) + 2 * rows;
+    }
+    std::vector<int> order((size_t)nr);
+    for (i64 r = 0; r < nr; ++r) order[r] = (int)r;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    const int G = b->gridB;
+    std::vector<std::pair<i64, int>> heap;  // (load, block), smallest load on top
+    for (int q = 0; q < G; ++q) heap.emplace_back(0, q);
+    auto cmp = [](const std::pair<i64, int> &x, const std::pair<i64, int> &y) {
+        return x.first != y.first ? x.first > y.first : x.second > y.second;
+    };
+    std::make_heap(heap.begin(), heap.end(), cmp);
+    std::vector<std::vector<int>> lists((size_t)G);
+    for (int r : order) {
+        std::pop_heap(heap.begin(), heap.end(), cmp);
+        auto &top = heap.back();
+        lists[top.second].push_back(r);
+        top.first += work[r];
+        std::push_heap(heap.begin(), heap.end(), cmp);
+    }
+    std::vector<int> ptr((size_t)G + 1, 0), flat;
+    flat.reserve((size_t)nr);
+    for (int q = 0; q < G; ++q) {
+        flat.insert(flat.end(), lists[q].begin(), lists[q].end());
+        ptr[q + 1] = (int)flat.size();
+    }
+    DI_HIP(hipMemcpy(b->blk_ptr, ptr.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice));
+    DI_HIP(hipMemcpy(b->blk_ranges, flat.data(), sizeof(int) * nr, hipMemcpyHostToDevice));
+    return DI_OK;
+}
+
+// Delivery units: the cross-range in-entries (grouped by target range, sorted by target
+// within it) are cut into units of at most DL_UNIT entries holding whole target rows;
+// a row with more entries gets units of its own, marked split.
+static int build_delivery_units(BatchState *b, const DevGraph &g) {
+    const i64 nr = g.nranges, mr = g.m_rem;
+    if (mr == 0) return DI_OK;
+    std::vector<i64> rbase(nr + 1);
+    std::vector<unsigned short> rt((size_t)mr);
+    DI_HIP(hipMemcpy(rbase.data(), g.rem_base, sizeof(i64) * (nr + 1), hipMemcpyDeviceToHost));
+    DI_HIP(hipMemcpy(rt.data(), g.rem_tgt, sizeof(unsigned short) * mr, hipMemcpyDeviceToHost));
+    std::vector<int> tabs((size_t)mr);
+    for (i64 r = 0; r < nr; ++r)
+        for (i64 p = rbase[r]; p < rbase[r + 1]; ++p) tabs[p] = (int)((r << g.rb) + rt[p]);
+    std::vector<DlUnit> units;
+    DlUnit cur{0, 0, 0};
+    for (i64 p = 0; p < mr;) {
+        i64 q = p + 1;
+        while (q < mr && tabs[q] == tabs[p]) ++q;
+        const i64 cnt = q - p;
+        if (cnt > DL_UNIT) {
+            if (cur.len) units.push_back(cur);
+            for (i64 e = p; e < q; e += DL_UNIT) units.push_back(DlUnit{e, (int)std::min<i64>(DL_UNIT, q - e), 1});
+            cur = DlUnit{q, 0, 0};
+        } else {
+            if (cur.len + cnt > DL_UNIT) {
+                units.push_back(cur);
+                cur = DlUnit{p, 0, 0};
+            }
+            if (cur.len == 0) cur.e0 = p;
+            cur.len += (int)cnt;
+        }
+        p = q;
+    }
+    if (cur.len) units.push_back(cur);
+    b->nunits = (i64)units.size();
+    b->gridD = (int)std::min<i64>(DL_GRID, (b->nunits + DL_WAVES - 1) / DL_WAVES);
+    if (hipMalloc((void **)&b->units, sizeof(DlUnit) * units.size()) != hipSuccess ||
+        hipMalloc((void **)&b->rem_tgt_abs, sizeof(int) * mr) != hipSuccess) {
+        set_error("device allocation of the delivery units failed");
+        return DI_ENOMEM;
+    }
+    DI_HIP(hipMemcpy(b->units, units.data(), sizeof(DlUnit) * units.size(), hipMemcpyHostToDevice));
+    DI_HIP(hipMemcpy(b->rem_tgt_abs, tabs.data(), sizeof(int) * mr, hipMemcpyHostToDevice));
+    return DI_OK;
+}
+
 int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int det, const double *Z,
-               hipStream_t st) {
+               const int *range_order, int rounds, hipStream_t st) {
     bout = nullptr;
     if (k < 1 || k > KMAX) {
         set_error("k must be in 1..%d", KMAX);
@@ -617,6 +1125,21 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
     const size_t T = p.fp32 ? 4 : 8;
     b->gridP = (int)std::min<i64>(TILE_GRID, (n + TILE_WAVES - 1) / TILE_WAVES);
     b->gridR = (int)std::min<i64>(REDUCE_TILE_GRID, (n + TILE_WAVES - 1) / TILE_WAVES);
+    // fast sweeps are block-local when a range's fluid and dH tiles fit in LDS
+    b->bld = !det && g.rb >= 6 && tile_bld_lds_launch(g.rb, k, (int)T) <= TB_LDS;
+    b->rounds = rounds > 0 ? rounds : 4;
+    (void)range_order;
+    if (b->bld) {
+        // as many resident workgroups as the compute units' LDS holds (160 KB each);
+        // ranges are dealt out longest first, each to the least loaded workgroup
+        int cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        const int per_cu = std::max(1, (int)((160 * 1024) / (tile_bld_lds_launch(g.rb, k, (int)T) + 1024)));
+        b->gridB = (int)std::min<i64>(std::min<i64>((i64)cus * std::min(per_cu, 2), TB_GRID), g.nranges);
+    }
+    const size_t slots = (size_t)std::max(std::max(b->gridR, b->gridP), b->gridB + DL_GRID);
     auto fail = [&](int code) {
         free_batch(b);
         return code;
@@ -627,10 +1150,21 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
         return false;
     };
     if (!alloc(&b->F, n * k * T) || !alloc((void **)&b->F0, n * k * 8) || !alloc((void **)&b->H, n * k * 8) ||
-        !alloc((void **)&b->ctl, sizeof(TileCtl)) || !alloc((void **)&b->partR, (size_t)b->gridR * KMAX * PSR * 8) ||
-        !alloc((void **)&b->partC, (size_t)b->gridP * KMAX * 4 * 8) ||
-        !alloc((void **)&b->partK, (size_t)b->gridP * 2 * 8) || (det && !alloc((void **)&b->snap, n * k * 8)))
+        !alloc((void **)&b->ctl, sizeof(TileCtl)) || !alloc((void **)&b->partR, slots * KMAX * PSR * 8) ||
+        !alloc((void **)&b->partC, slots * KMAX * 4 * 8) || !alloc((void **)&b->partK, slots * 2 * 8) ||
+        (det && !alloc((void **)&b->snap, n * k * 8)))
         return fail(DI_ENOMEM);
+    if (b->bld) {
+        if (!alloc(&b->S, n * k * T) || !alloc((void **)&b->fl, n) ||
+            !alloc((void **)&b->blk_ptr, (size_t)(b->gridB + 1) * 4) ||
+            !alloc((void **)&b->blk_ranges, (size_t)g.nranges * 4))
+            return fail(DI_ENOMEM);
+        int src = assign_ranges(b, g);
+        if (src == DI_OK) src = build_delivery_units(b, g);
+        if (src != DI_OK) return fail(src);
+        const int arc = set_tile_attributes();
+        if (arc != DI_OK) return fail(arc);
+    }
     if (hipHostMalloc((void **)&b->h_ctl, sizeof(TileCtl), hipHostMallocDefault) != hipSuccess) {
         set_error("hipHostMalloc failed");
         return fail(DI_ENOMEM);
@@ -652,8 +1186,9 @@ int reset_batch(BatchState *b, const DevGraph &g, const SweepParams &p, hipStrea
     DI_TRY(launch_init_fluid(b->F0, b->F, b->fp32, b->n * b->k, st));
     DI_TRY(launch_fill_zero(b->H, b->n * b->k * 8, st));
     DI_TRY(launch_fill_zero(b->ctl, sizeof(TileCtl), st));
+    if (b->bld) DI_TRY(launch_fill_zero(b->fl, b->n, st));
     DI_TRY(launch_tile_reduce(b, tile_args(b, g, p), 1, st));
-    DI_TRY(launch_tile_finalize(b, p, FIN_INIT, st));
+    DI_TRY(launch_tile_finalize(b, p, FIN_INIT, b->gridR, 0, 0, st));
     DI_HIP(hipStreamSynchronize(st));
     return DI_OK;
 }
@@ -710,7 +1245,7 @@ int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const 
     k_tile_begin<<<1, 1, 0, st>>>(b->ctl, (long long)o.max_sweeps);
     DI_LAUNCH_CHECK();
     DI_TRY(launch_tile_reduce(b, tile_args(b, g, p), 1, st));
-    DI_TRY(launch_tile_finalize(b, p, FIN_INIT, st));
+    DI_TRY(launch_tile_finalize(b, p, FIN_INIT, b->gridR, 0, 0, st));
     DI_TRY(sync_tile(b, st));
     const TileCtl before = *b->h_ctl;
     auto max_R = [&](const TileCtl &h) {

@@ -397,8 +397,11 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     if (opt.n_graphs > 1 && opt.k > 1) DI_FAIL(DI_EINVAL, "k > 1 with n_graphs > 1 is not supported");
     if (opt.max_sweeps < 0) DI_FAIL(DI_EINVAL, "max_sweeps must be >= 0");
     if (opt.max_sweeps == 0) opt.max_sweeps = 100000;
-    if (opt.range_log2 != 0 && (opt.range_log2 < 8 || opt.range_log2 > (opt.fluid_fp32 ? 14 : 13)))
-        DI_FAIL(DI_EINVAL, "range_log2 must be 0 or in 8..%d", opt.fluid_fp32 ? 14 : 13);
+    {
+        const int lo = opt.k > 1 ? 6 : 8, hi = opt.fluid_fp32 ? 14 : 13;
+        if (opt.range_log2 != 0 && (opt.range_log2 < lo || opt.range_log2 > hi))
+            DI_FAIL(DI_EINVAL, "range_log2 must be 0 or in %d..%d", lo, hi);
+    }
     if (opt.inner_rounds < 0 || opt.inner_rounds > 64) DI_FAIL(DI_EINVAL, "inner_rounds must be in 0..64");
     if (opt.loop_mode != DI_LOOP_STREAM && opt.loop_mode != DI_LOOP_GRAPH) DI_FAIL(DI_EINVAL, "bad loop_mode");
     if (opt.sweeps_per_sync < 0) DI_FAIL(DI_EINVAL, "sweeps_per_sync must be >= 0");
@@ -464,7 +467,11 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     // at least ~256 nodes per range so that several workgroups run
     const int rbmax = opt.fluid_fp32 ? 14 : 13;
     int rb = opt.range_log2;
-    if (rb == 0) {
+    if (rb == 0 && opt.k > 1 && !opt.deterministic) {
+        // several columns: ranges whose k-column fluid and dH tiles fit in LDS
+        rb = tile_range_log2(opt.k, opt.fluid_fp32);
+        if (rb == 0) rb = 8;
+    } else if (rb == 0) {
         const int cap = w ? rbmax : 11;
         rb = 8;
         while (rb < cap && ((i64)1 << (rb + 1)) * 256 <= n) ++rb;
@@ -592,7 +599,8 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
 
     // initial fluid F_0 = (1-d) Z, rounded to float in the float-fluid mode; fixed-point scale
     if (k > 1) {
-        if ((rc = init_batch(c->b, c->g, c->p, k, opt.deterministic ? 1 : 0, Z, c->st)) != DI_OK) return fail(rc);
+        if ((rc = init_batch(c->b, c->g, c->p, k, opt.deterministic ? 1 : 0, Z, c->s.range_order, c->rounds, c->st)) != DI_OK)
+            return fail(rc);
         c->p.K = batch_K(c->b);
         *out = c;
         return DI_OK;
