@@ -27,24 +27,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def di_algorithmic_bytes(s, n, st_sweeps, fp32):
-    """Bytes the block-local sweep must move (per-unit model)."""
-    from paper_1501_06350_amd import binding as B
-    T = 4 if fp32 else 8
-    m_rem = s.info(B.INFO_M_REMOTE)
-    nr = s.info(B.INFO_NRANGES)
-    local = s.info(B.INFO_LOCAL_PUSHES)
-    return {
-        # per sweep: F read + write, in-flight write, cross-range entries (src 4 + tgt 2 + gather T)
-        "per_sweep": n * 3 * T + m_rem * (6 + T) + nr * 16,
-        # per diffusion: H read+write 16, 1/s_j 8, remote weight 8, local row pointers 16
-        "per_diffusion": 48,
-        # per local push: 2-byte target index (the update itself stays in LDS)
-        "per_local_push": 2,
-        "local_pushes": local,
-    }
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +41,8 @@ def main():
     ap.add_argument("--range-log2", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=0)
     ap.add_argument("--theta", type=float, default=1.0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for rocprofv3 --pmc runs: a copy of known size, then one DI solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has a single MI355X, and the multi-GPU "
@@ -73,6 +57,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     fp32 = not args.fp64
+    if args.traffic_probe:
+        traffic_probe(args, fp32)
+        return
     t0 = time.time()
     g = W.webgen(args.n, args.seed)
     log("graph webgen(n=%d, seed=%d): m=%d generated in %.1fs" % (g.n, args.seed, g.m, time.time() - t0))
@@ -173,8 +160,8 @@ def main():
                             "unit": "GB/s", "frac": round(pi_achieved / HBM_PEAK_GBS, 4)}},
         "di_pi_l1_diff": di_pi_l1,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_bld_sweep", "launches": kern_launch, "avg_us": round(avg_ns / 1e3, 2)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "kernel": "k_bld2_sweep", "launches": kern_launch, "avg_us": round(avg_ns / 1e3, 2)},
     }
     s.close()
     del xd, xp
@@ -190,6 +177,55 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(g, args.cpu_sweeps)
     print(json.dumps(result), flush=True)
+
+
+COPY_BYTES = 1 << 30
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_k_bld2_sweep_webgen50m.md")
+
+
+def sweep_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1501_06350_amd", "csrc", "sweep.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the block-local sweep from the committed counter profile,
+    or None when the kernel source changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("- "):
+            key, val = line[2:].split(":", 1)
+            vals[key.strip()] = val.strip().strip("`")
+    if vals.get("sweep.hip sha256") != sweep_source_hash():
+        return None
+    try:
+        return float(vals["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def traffic_probe(args, fp32):
+    """Three copies of a known size (the counter scale), then one D-Iteration solve on the
+    headline graph; run under rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE."""
+    import torch
+    import workloads as W
+    from paper_1501_06350_amd import binding as B
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    g = W.webgen(args.n, args.seed)
+    with B.from_graph(g, d=D, fluid_fp32=fp32) as s:
+        st = s.diffuse(TOL)
+    torch.cuda.synchronize()
+    log("traffic probe: copies of %d bytes, then %d sweeps, sweep.hip sha256 %s" %
+        (COPY_BYTES, st["sweeps"], sweep_source_hash()))
 
 
 def _timed(fn):

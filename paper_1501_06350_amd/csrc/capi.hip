@@ -178,8 +178,8 @@ int reset_state(di_ctx *c) {
     const size_t T = c->p.fp32 ? 4 : 8;
     DI_TRY(launch_init_fluid(c->s.F0, c->s.F, c->p.fp32, n, c->st));
     DI_TRY(launch_fill_zero(c->s.H, n * 8, c->st));
-    DI_TRY(launch_fill_zero(c->s.S[0], n * T, c->st));
-    DI_TRY(launch_fill_zero(c->s.S[1], n * T, c->st));
+    DI_TRY(launch_fill_zero(c->s.S[0], c->s.S_bytes, c->st));
+    DI_TRY(launch_fill_zero(c->s.S[1], c->s.S_bytes, c->st));
     DI_TRY(launch_fill_zero(c->s.ctl, sizeof(DevCtl), c->st));
     if (c->s.gctl) DI_TRY(launch_fill_zero(c->s.gctl, sizeof(GraphCtl) * c->s.n_graphs, c->st));
     DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st));
@@ -202,8 +202,8 @@ int refine_fluid(di_ctx *c, double tol) {
     if (!c->ref_ht) DI_TRY(dalloc(c, &c->ref_ht, c->g.n));
     DI_TRY(launch_bld_sweep(c->g, c->s, c->p, 0, c->st));
     DI_TRY(enqueue_finalize(c, FIN_DELIVER, c->st));
-    DI_TRY(launch_fill_zero(c->s.S[0], c->g.n * T, c->st));
-    DI_TRY(launch_fill_zero(c->s.S[1], c->g.n * T, c->st));
+    DI_TRY(launch_fill_zero(c->s.S[0], c->s.S_bytes, c->st));
+    DI_TRY(launch_fill_zero(c->s.S[1], c->s.S_bytes, c->st));
     DI_TRY(launch_refine_fluid(c->g, c->rbin, c->s, c->p, c->ref_ht, c->st));
     if (!c->s.range_graph) {
         k_ctl_reopen<<<1, 1, 0, c->st>>>(c->s.ctl);
@@ -565,7 +565,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     c->rounds = opt.inner_rounds ? opt.inner_rounds : 4;
     c->p.rounds = c->rounds;
     c->spc = opt.sweeps_per_sync ? opt.sweeps_per_sync : 8;
-    if ((rc = build_graph(c->g, c->g.out_ptr, c->g.out_idx, c->g.w, rb, c->st)) != DI_OK) return fail(rc);
+    if ((rc = build_graph(c->g, c->g.out_ptr, c->g.out_idx, c->g.w, rb, k == 1, c->st)) != DI_OK) return fail(rc);
     c->device_bytes += (2 * (n + 1) + 3 * n) * 8 + m * (4 + (w ? 4 : 0)) + c->g.m_loc * (2 + (w ? 4 : 0)) +
                        c->g.m_rem * (6 + (w ? 4 : 0)) + (c->g.nranges + 1) * 16;
 
@@ -619,10 +619,15 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         mx = std::max(mx, std::fabs(c->p.fp32 ? (double)(float)v : v));
     }
     c->p.K = fixed_scale(mx, n);
+    // in-flight buffers: n values, then a bitmap of the nonzero ones (n/64 words)
+    const i64 s_vals = ((i64)(n * T) + 255) & ~(i64)255;
+    c->s.S_bytes = s_vals + ((n + 63) / 64) * 8;
     if ((rc = dalloc(c, (char **)&c->s.F, n * T)) || (rc = dalloc(c, &c->s.F0, n)) ||
-        (rc = dalloc(c, &c->s.H, n)) || (rc = dalloc(c, (char **)&c->s.S[0], n * T)) ||
-        (rc = dalloc(c, (char **)&c->s.S[1], n * T)) || (rc = dalloc(c, &c->s.ctl, 1)))
+        (rc = dalloc(c, &c->s.H, n)) || (rc = dalloc(c, (char **)&c->s.S[0], c->s.S_bytes)) ||
+        (rc = dalloc(c, (char **)&c->s.S[1], c->s.S_bytes)) || (rc = dalloc(c, &c->s.ctl, 1)))
         return fail(rc);
+    c->s.Sb[0] = reinterpret_cast<u64 *>(static_cast<char *>(c->s.S[0]) + s_vals);
+    c->s.Sb[1] = reinterpret_cast<u64 *>(static_cast<char *>(c->s.S[1]) + s_vals);
     if (hipMemcpy(c->s.F0, f0.data(), n * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DI_EHIP);
     if (Z && c->n_graphs == 1) {  // power iteration reads Z (one graph only)
         if ((rc = dalloc(c, &c->s.Z, n))) return fail(rc);
@@ -751,8 +756,8 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
         // every call starts with no fluid in flight (the last one delivered it): clear the
         // in-flight buffers, then set each graph's state under the new tolerance
         const size_t T = c->p.fp32 ? 4 : 8;
-        DI_TRY(launch_fill_zero(c->s.S[0], c->g.n * T, c->st));
-        DI_TRY(launch_fill_zero(c->s.S[1], c->g.n * T, c->st));
+        DI_TRY(launch_fill_zero(c->s.S[0], c->s.S_bytes, c->st));
+        DI_TRY(launch_fill_zero(c->s.S[1], c->s.S_bytes, c->st));
         k_ctl_begin<<<1, 1, 0, c->st>>>(c->s.ctl, (long long)c->o.max_sweeps);
         DI_LAUNCH_CHECK();
         DI_TRY(launch_reduce_F(c->g, c->s, c->p, c->st, 0));
@@ -1207,8 +1212,8 @@ int di_load(di_ctx *c, const char *path) {
     if (!ok) DI_FAIL(DI_EINVAL, "%s is not a checkpoint of this graph, d and precision", path);
     DI_HIP(hipMemcpy(c->s.H, H.data(), sizeof(double) * n, hipMemcpyHostToDevice));
     DI_HIP(hipMemcpy(c->s.F, F.data(), T * n, hipMemcpyHostToDevice));
-    DI_TRY(launch_fill_zero(c->s.S[0], n * T, c->st));
-    DI_TRY(launch_fill_zero(c->s.S[1], n * T, c->st));
+    DI_TRY(launch_fill_zero(c->s.S[0], c->s.S_bytes, c->st));
+    DI_TRY(launch_fill_zero(c->s.S[1], c->s.S_bytes, c->st));
     DI_TRY(launch_fill_zero(c->s.ctl, sizeof(DevCtl), c->st));
     k_ctl_restore<<<1, 1, 0, c->st>>>(c->s.ctl, (long long)h.sweep, h.limbsL[0], h.limbsL[1], h.limbsL[2],
                                       h.limbsL[3], h.tot_nodes, h.tot_edges);

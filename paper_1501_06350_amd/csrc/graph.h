@@ -35,7 +35,10 @@ struct DevGraph {
 
 int scan_exclusive(const i64 *in, i64 *out, i64 count, i64 *temp, hipStream_t st);
 i64 scan_temp_elems(i64 count);
+// remote_by_source: order each range's cross-range entries by source (the single
+// right-hand-side pull) instead of by target (the k-column delivery needs target order)
 int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const float *d_w, int range_log2,
+                bool remote_by_source,
                 hipStream_t st);
 void free_graph(DevGraph &g);
 

@@ -355,6 +355,40 @@ __global__ void k_remote_scatter(const unsigned *__restrict__ tgt, const int *__
     if (rem_w) rem_w[q] = in_w[p];
 }
 
+// Re-ordering of each range's cross-range entries by source (see build_graph).
+__global__ void k_iota_keys(const int *__restrict__ src, i64 m, unsigned *keys, u64 *vals) {
+    i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    keys[p] = (unsigned)src[p];
+    vals[p] = (u64)p;
+}
+
+// keys[i] = the range whose entries hold original position pos[i]
+__global__ void k_range_of(const u64 *__restrict__ pos, i64 m, const i64 *__restrict__ rem_base, i64 nranges,
+                           unsigned *keys) {
+    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const i64 q = (i64)pos[i];
+    i64 lo = 0, hi = nranges - 1;  // last r with rem_base[r] <= q
+    while (lo < hi) {
+        const i64 mid = (lo + hi + 1) >> 1;
+        if (rem_base[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    keys[i] = (unsigned)lo;
+}
+
+__global__ void k_permute_remote(const u64 *__restrict__ pos, i64 m, const int *__restrict__ src,
+                                 const unsigned short *__restrict__ tgt, const float *__restrict__ w, int *src2,
+                                 unsigned short *tgt2, float *w2) {
+    i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const i64 q = (i64)pos[i];
+    src2[i] = src[q];
+    tgt2[i] = tgt[q];
+    if (w) w2[i] = w[q];
+}
+
 __global__ void k_deg_flags(const i64 *__restrict__ out_ptr, const double *__restrict__ rw, i64 n, unsigned *out) {
     i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -386,6 +420,7 @@ static int dalloc(T **p, i64 count) {
 }
 
 int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const float *d_w, int range_log2,
+                bool remote_by_source,
                 hipStream_t st) {
     const i64 n = g.n, m = g.m;
     const int TB = 256;
@@ -473,6 +508,41 @@ int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const f
     k_range_bases<<<grid_for(g.nranges + 1, TB), TB, 0, st>>>(g.in_ptr, flag, n, m, g.m_rem, rb, g.nranges,
                                                               g.rem_base, g.loc_ptr, g.loc_base);
     DI_LAUNCH_CHECK();
+    // Within each range, order the cross-range entries by source instead of by target:
+    // a range's pull then walks the in-flight values of each neighbouring range in
+    // address order, so most gathers hit lines already in cache.  (Two stable passes:
+    // by source, then by range.)
+    if (remote_by_source && g.m_rem > 1) {
+        const i64 mr = g.m_rem;
+        int sbits = 1, rbits = 1;
+        while (((i64)1 << sbits) < n) ++sbits;
+        while (((i64)1 << rbits) < g.nranges) ++rbits;
+        k_iota_keys<<<grid_for(mr, TB), TB, 0, st>>>(g.rem_src, mr, keys, vals);
+        DI_LAUNCH_CHECK();
+        bool t1 = false, t2 = false;
+        DI_TRY(radix_sort_pairs<u64>(keys, vals, keys2, vals2, mr, sbits, counts, stemp, st, &t1));
+        unsigned *k1 = t1 ? keys2 : keys, *k1o = t1 ? keys : keys2;
+        u64 *v1 = t1 ? vals2 : vals, *v1o = t1 ? vals : vals2;
+        k_range_of<<<grid_for(mr, TB), TB, 0, st>>>(v1, mr, g.rem_base, g.nranges, k1);
+        DI_LAUNCH_CHECK();
+        DI_TRY(radix_sort_pairs<u64>(k1, v1, k1o, v1o, mr, rbits, counts, stemp, st, &t2));
+        const u64 *perm = t2 ? v1o : v1;
+        int *src2 = nullptr;
+        unsigned short *tgt2 = nullptr;
+        float *w2 = nullptr;
+        DI_TRY(dalloc(&src2, mr));
+        DI_TRY(dalloc(&tgt2, mr));
+        if (g.weighted) DI_TRY(dalloc(&w2, mr));
+        k_permute_remote<<<grid_for(mr, TB), TB, 0, st>>>(perm, mr, g.rem_src, g.rem_tgt, g.rem_w, src2, tgt2, w2);
+        DI_LAUNCH_CHECK();
+        DI_HIP(hipStreamSynchronize(st));
+        (void)hipFree(g.rem_src);
+        (void)hipFree(g.rem_tgt);
+        if (g.rem_w) (void)hipFree(g.rem_w);
+        g.rem_src = src2;
+        g.rem_tgt = tgt2;
+        g.rem_w = w2;
+    }
     DI_HIP(hipStreamSynchronize(st));
 
     (void)hipFree(keys);

@@ -58,6 +58,8 @@ struct SolveState {
     double *F0 = nullptr;    // n initial fluid (1-d) Z, in double for every fluid type
     double *H = nullptr;     // n history
     void *S[2] = {nullptr, nullptr};  // n fluid in flight to other ranges (parity by ctl->parity)
+    u64 *Sb[2] = {nullptr, nullptr};  // bit i of word i/64: S[.][i] is nonzero (same allocation as S)
+    i64 S_bytes = 0;                  // bytes of each S allocation (values, then the bitmap)
     double *snap = nullptr;  // n deterministic sweep: pushed value per source
     int *frontier = nullptr; // n deterministic sweep: active set of the last sweep
     int *range_order = nullptr;  // nranges, heaviest first

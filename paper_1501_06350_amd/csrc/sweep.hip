@@ -66,6 +66,7 @@ struct BldArgs {
     void *F;
     double *H;
     void *S0, *S1;
+    u64 *Sb0, *Sb1;  // bitmaps of the nonzero in-flight values
     DevCtl *ctl;
     double d;
     int K;
@@ -109,6 +110,8 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
     const int par = ctl->parity;
     const T *Sprev = reinterpret_cast<const T *>(par ? a.S1 : a.S0);
     T *Snext = reinterpret_cast<T *>(par ? a.S0 : a.S1);
+    const u64 *Sbprev = par ? a.Sb1 : a.Sb0;
+    u64 *Sbnext = par ? a.Sb0 : a.Sb1;
     T *F = reinterpret_cast<T *>(a.F);
     double thr = ctl->thr;
     int rounds = a.rounds;
@@ -142,9 +145,13 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
                 tg[u] = (unsigned)a.rem_tgt[p];
                 wv[u] = WTD ? a.rem_w[p] : 1.0f;
             }
+            // a value is gathered only when its bit in the in-flight bitmap is set
+            u64 wd[REM_U];
+#pragma unroll
+            for (int u = 0; u < REM_U; ++u) wd[u] = Sbprev[src[u] >> 6];
             T v[REM_U];
 #pragma unroll
-            for (int u = 0; u < REM_U; ++u) v[u] = Sprev[src[u]];
+            for (int u = 0; u < REM_U; ++u) v[u] = ((wd[u] >> (src[u] & 63)) & 1ull) ? Sprev[src[u]] : (T)0;
 #pragma unroll
             for (int u = 0; u < REM_U; ++u) {
                 if (pb + (i64)u * BLD_THREADS < p1 && v[u] != (T)0) {
@@ -238,7 +245,10 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
         const T v = Fl[i];
         const T s = Sl[i];
         F[base + i] = v;
-        Snext[base + i] = s;
+        // the wave's 64 lanes hold 64 consecutive nodes starting at a multiple of 64
+        const u64 bits = __ballot(s != (T)0);
+        if (s != (T)0) Snext[base + i] = s;
+        if ((threadIdx.x & (WAVE - 1)) == 0) Sbnext[(base + i) >> 6] = bits;
         if (!limbs_add_checked(R, fabs((double)v), a.K)) bad = 1;
         if (s != (T)0 && !limbs_add_checked(R, fabs((double)s) * a.rw[base + i], a.K)) bad = 1;
     }
@@ -265,6 +275,8 @@ static BldArgs make_bld_args(const DevGraph &g, SolveState &s, const SweepParams
     a.H = s.H;
     a.S0 = s.S[0];
     a.S1 = s.S[1];
+    a.Sb0 = s.Sb[0];
+    a.Sb1 = s.Sb[1];
     a.ctl = s.ctl;
     a.d = p.d;
     a.K = p.K;
@@ -303,6 +315,7 @@ struct Bld2Args {
     void *F;
     double *H;
     void *S0, *S1;
+    u64 *Sb0, *Sb1;
     DevCtl *ctl;
     double d;
     int K;
@@ -348,6 +361,8 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     const int par = ctl->parity;
     const T *Sprev = reinterpret_cast<const T *>(par ? a.S1 : a.S0);
     T *Snext = reinterpret_cast<T *>(par ? a.S0 : a.S1);
+    const u64 *Sbprev = par ? a.Sb1 : a.Sb0;
+    u64 *Sbnext = par ? a.Sb0 : a.Sb1;
     T *F = reinterpret_cast<T *>(a.F);
     double thr = ctl->thr;
     int rounds = a.rounds;
@@ -408,7 +423,9 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     }
     __syncthreads();
 
-    // 2. fluid sent here by other ranges last sweep
+    // 2. fluid sent here by other ranges last sweep; a source's value is gathered only
+    // when its bit in the in-flight bitmap is set (most sources send nothing in a sweep,
+    // and a random 4-byte gather costs a full line)
     u64 delivered = 0;
     {
         constexpr int REM_U = 8;
@@ -422,9 +439,12 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                 src[u] = a.rem_src[p];
                 tg[u] = (unsigned)a.rem_tgt[p];
             }
+            u64 wd[REM_U];
+#pragma unroll
+            for (int u = 0; u < REM_U; ++u) wd[u] = Sbprev[src[u] >> 6];
             T v[REM_U];
 #pragma unroll
-            for (int u = 0; u < REM_U; ++u) v[u] = Sprev[src[u]];
+            for (int u = 0; u < REM_U; ++u) v[u] = ((wd[u] >> (src[u] & 63)) & 1ull) ? Sprev[src[u]] : (T)0;
 #pragma unroll
             for (int u = 0; u < REM_U; ++u) {
                 if (pb + (i64)u * nthr < p1 && v[u] != (T)0) {
@@ -526,10 +546,13 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int i = i0 + u * nthr;
+            // the wave's 64 lanes hold 64 consecutive nodes starting at a multiple of 64
+            const u64 bits = __ballot(i < cnt && sv[u] != (T)0);
             if (i < cnt) {
                 const T v = Fl[i];
                 F[base + i] = v;
-                Snext[base + i] = sv[u];
+                if (sv[u] != (T)0) Snext[base + i] = sv[u];
+                if ((threadIdx.x & (WAVE - 1)) == 0) Sbnext[(base + i) >> 6] = bits;
                 if (dh[u] != 0.0) a.H[base + i] = hv[u] + dh[u];
                 if (!limbs_add_checked(R, fabs((double)v), a.K)) bad = 1;
                 if (sv[u] != (T)0 && !limbs_add_checked(R, fabs((double)sv[u]) * rwv[u], a.K)) bad = 1;
@@ -577,6 +600,8 @@ int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int
         b.H = s.H;
         b.S0 = s.S[0];
         b.S1 = s.S[1];
+        b.Sb0 = s.Sb[0];
+        b.Sb1 = s.Sb[1];
         b.ctl = s.ctl;
         b.d = p.d;
         b.K = p.K;
