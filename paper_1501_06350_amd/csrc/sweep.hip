@@ -459,8 +459,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     // 3. local rounds (LDS only); wave w owns [my0, my1)
     const int sub = (((cnt + nw - 1) / nw) + WAVE - 1) & ~(WAVE - 1);
     const int my0 = w * sub, my1 = min(cnt, my0 + sub);
-    Limbs leak;
-    limbs_zero(leak);
+    double Ld = 0.0;  // this lane's leak, added to the exact sum once at the end
     u64 nodes = 0, edges = 0;
     for (int round = 0; round < rounds; ++round) {
         bool any = false;
@@ -480,7 +479,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                 Dl[i] = (T)((double)Dl[i] + f);
                 const unsigned deg = Deg[i] & 0x7fffffffu;
                 if (deg == 0) {
-                    if (!limbs_add_checked(leak, fabs(f), a.K)) bad = 1;
+                    Ld += fabs(f);
                 } else {
                     q = (a.d * f) * (1.0 / (double)deg);
                     st = Off[i];
@@ -488,31 +487,62 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                 }
                 ++nodes;
             }
+            // the nodes with edges to push, listed in lane order: their edge lists are
+            // consecutive in the slot space [0, total)
+            const u64 pm = __ballot(dg > 0);
+            const int nact = __popcll(pm);
             const int inc = wave_incl_scan_i32(dg);
             const int total = __shfl(inc, WAVE - 1, WAVE);
-            sc_start[lane] = st;
-            sc_off[lane] = inc - dg;
-            sc_q[lane] = q;
+            if (dg > 0) {
+                const int rk = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(pm >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)pm, 0u));
+                sc_start[rk] = st;
+                sc_off[rk] = inc - dg;
+                sc_q[rk] = q;
+            }
             wave_sync_lds();
             edges += (lane == 0) ? (u64)total : 0ull;
+            // binary search depth over the nact listed nodes (uniform across the wave)
+            const int depth = nact > 1 ? 32 - __builtin_clz((unsigned)(nact - 1)) : 0;
             constexpr int EDGE_U = 4;
             for (int sb = lane; sb < total; sb += WAVE * EDGE_U) {
                 unsigned tgt[EDGE_U];
                 double val[EDGE_U];
+                unsigned pp[EDGE_U];
 #pragma unroll
                 for (int u = 0; u < EDGE_U; ++u) {
                     const int s = min(sb + u * WAVE, total - 1);
-                    int lo = 0, hi = WAVE - 1;  // last k with sc_off[k] <= s (it has a nonzero degree)
-#pragma unroll
-                    for (int it = 0; it < 6; ++it) {
+                    int lo = 0, hi = nact - 1;  // last listed node k with sc_off[k] <= s
+                    for (int it = 0; it < depth; ++it) {
                         const int mid = (lo + hi + 1) >> 1;
                         const bool le = sc_off[mid] <= s;
                         lo = le ? mid : lo;
                         hi = le ? hi : mid - 1;
                     }
-                    const unsigned p = sc_start[lo] + (unsigned)(s - sc_off[lo]);
-                    tgt[u] = (int)p < ncap ? (unsigned)Tg[tdelta + p] : (unsigned)a.loc_tgt[lb + p];
+                    pp[u] = sc_start[lo] + (unsigned)(s - sc_off[lo]);
                     val[u] = sc_q[lo];
+                }
+                // targets from the staged LDS copy when every slot of the batch lies in it
+                // (the usual case), else per slot from LDS or global memory (the empty asm
+                // keeps the two loads apart, so the LDS one stays an LDS access)
+                bool staged = true;
+#pragma unroll
+                for (int u = 0; u < EDGE_U; ++u) staged = staged && (int)pp[u] < ncap;
+                if (__ballot(!staged) == 0) {
+#pragma unroll
+                    for (int u = 0; u < EDGE_U; ++u) tgt[u] = Tg[tdelta + pp[u]];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < EDGE_U; ++u) {
+                        unsigned t;
+                        if ((int)pp[u] < ncap) {
+                            t = Tg[tdelta + pp[u]];
+                        } else {
+                            t = a.loc_tgt[lb + pp[u]];
+                            asm volatile("" : "+v"(t));
+                        }
+                        tgt[u] = t;
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < EDGE_U; ++u)
@@ -527,8 +557,11 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     // 4. write back: F, H += dH, cross-range share for the next sweep, residual.
     // Untouched nodes point their H and rw loads at the range's first node (an address
     // every thread loads), so the batch needs no branches around its loads.
+    // residual: each lane sums its (at most 2 * 2^rb / blockDim) terms in double, raises
+    // the sum by 2^-40 relative (far above that rounding) and adds it to the exact sum once
     Limbs R;
     limbs_zero(R);
+    double Rd = 0.0;
     for (int i0 = threadIdx.x; i0 < cnt; i0 += nthr * SU) {
         double hv[SU], rwv[SU], dh[SU];
         T sv[SU];
@@ -554,11 +587,15 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                 if (sv[u] != (T)0) Snext[base + i] = sv[u];
                 if ((threadIdx.x & (WAVE - 1)) == 0) Sbnext[(base + i) >> 6] = bits;
                 if (dh[u] != 0.0) a.H[base + i] = hv[u] + dh[u];
-                if (!limbs_add_checked(R, fabs((double)v), a.K)) bad = 1;
-                if (sv[u] != (T)0 && !limbs_add_checked(R, fabs((double)sv[u]) * rwv[u], a.K)) bad = 1;
+                Rd += fabs((double)v);
+                if (sv[u] != (T)0) Rd += fabs((double)sv[u]) * rwv[u];
             }
         }
     }
+    if (!limbs_add_checked(R, Rd * (1.0 + 0x1p-40), a.K)) bad = 1;
+    Limbs leak;
+    limbs_zero(leak);
+    if (!limbs_add_checked(leak, Ld, a.K)) bad = 1;
     store_residual_partial(R, 0, red, a.partR + (i64)r * PSR);
     store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)r * PSC);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
