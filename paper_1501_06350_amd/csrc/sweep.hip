@@ -307,7 +307,6 @@ struct Bld2Args {
     const int *rem_src;
     const unsigned short *rem_tgt;
     const i64 *rem_base;
-    const double *rw;
     const int *range_order;
     i64 n;
     int rb;
@@ -555,8 +554,8 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     __syncthreads();
 
     // 4. write back: F, H += dH, cross-range share for the next sweep, residual.
-    // Untouched nodes point their H and rw loads at the range's first node (an address
-    // every thread loads), so the batch needs no branches around its loads.
+    // Untouched nodes point their H load at the range's first node (an address every
+    // thread loads), so the batch needs no branches around its loads.
     // residual: each lane sums its (at most 2 * 2^rb / blockDim) terms in double, raises
     // the sum by 2^-40 relative (far above that rounding) and adds it to the exact sum once
     Limbs R;
@@ -574,7 +573,8 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                         ? (T)((a.d * dh[u]) * (1.0 / (double)(df & 0x7fffffffu)))
                         : (T)0;
             hv[u] = a.H[base + (dh[u] != 0.0 ? i : 0)];
-            rwv[u] = a.rw[base + (sv[u] != (T)0 ? i : 0)];
+            // cross-range out-degree (the graph is unweighted): degree minus local degree
+            rwv[u] = (double)((df & 0x7fffffffu) - (Off[i + 1] - Off[i]));
         }
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
@@ -628,7 +628,6 @@ int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int
         b.rem_src = g.rem_src;
         b.rem_tgt = g.rem_tgt;
         b.rem_base = g.rem_base;
-        b.rw = g.rw;
         b.range_order = s.range_order;
         b.n = g.n;
         b.rb = g.rb;
