@@ -328,6 +328,11 @@ def test_union_256_graph_workload(gpu):
             x = s1.read(gpu.H)
         err = np.abs(H[lo:hi] - x).sum()
         assert err <= R[q] / (1 - D) * (1 + 1e-7) + 1e-12 / (1 - D), (q, err)
+        # the oracle's exact residual of the graph's history certifies it on its own
+        og = O.OGraph(hi - lo, ptr, idx)
+        Hq = H[lo:hi]
+        Rq = float(np.abs((1 - D) / (hi - lo) + D * og.P_times(Hq) - Hq).sum())
+        assert Rq / (1 - D) <= 1e-8 * (1 + 1e-6), (q, Rq)
 
 
 # ---------------------------------------------------------------------------
