@@ -35,6 +35,8 @@ struct di_ctx {
     DevGraph g;
     RowBlocks rbin;  // row blocks of IN (power iteration, fluid recomputation)
     bool rbin_ready = false;
+    RowBlocks rbout;  // row blocks of OUT (fast adjoint)
+    bool rbout_ready = false;
     double *ref_ht = nullptr;  // n doubles: H / s for the fluid recomputation
     SolveState s;
     SweepParams p;
@@ -357,6 +359,7 @@ int di_destroy(di_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     free_graph(c->g);
     free_row_blocks(c->rbin);
+    free_row_blocks(c->rbout);
     void *ps[] = {c->s.F, c->s.F0, c->s.H, c->s.S[0], c->s.S[1], c->s.snap, c->s.frontier, c->s.range_order,
                   c->s.ctl, c->s.X[0], c->s.X[1], c->s.XT[0], c->s.XT[1], c->s.pctl, c->s.Z, c->lam,
                   c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.ginfo, c->s.gctl,
@@ -1092,10 +1095,20 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ_INIT, c->st, c->s.partR, anR, c->s.partC, 0));
     DI_TRY(sync_ctl(c, c->actl));
     DevCtl before = *c->h_ctl;
+    // deterministic contexts: snapshot and a row-order pull (reproducible, the oracle's
+    // order); otherwise the same snapshot and a wave-per-row-block pull
+    if (!c->o.deterministic && !c->rbout_ready) {
+        DI_TRY(build_row_blocks(c->rbout, c->g.out_ptr, n, c->st));
+        c->rbout_ready = true;
+    }
     while (!c->h_ctl->done) {
         for (int k = 0; k < c->spc; ++k) {
-            DI_TRY(launch_adj_sweep(c->g, c->aF, c->lam, c->asnap, c->actl, ap, c->st, c->s.partR, c->s.partC, &anR,
-                                    &anC));
+            if (c->o.deterministic)
+                DI_TRY(launch_adj_sweep(c->g, c->aF, c->lam, c->asnap, c->actl, ap, c->st, c->s.partR, c->s.partC,
+                                        &anR, &anC));
+            else
+                DI_TRY(launch_adj_sweep_fast(c->g, c->rbout, c->aF, c->lam, c->asnap, c->actl, ap, c->st, c->s.partR,
+                                             c->s.partC, &anR, &anC));
             DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ, c->st, c->s.partR, anR, c->s.partC, anC));
         }
         DI_TRY(sync_ctl(c, c->actl));

@@ -135,6 +135,10 @@ int launch_mg_finalize(SolveState &s, DevCtl *ctl, const SweepParams &p, int mod
 
 int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevCtl *ctl, const SweepParams &p,
                      hipStream_t st, u64 *partR, u64 *partC, i64 *nR, i64 *nC);
+// Fast adjoint sweep: the same snapshot, then a wave-per-row-block pull over OUT (rb_out:
+// row blocks of OUT) that also sums the residual; additions in lane order, not row order.
+int launch_adj_sweep_fast(const DevGraph &g, const RowBlocks &rb_out, double *F, double *H, double *snap, DevCtl *ctl,
+                          const SweepParams &p, hipStream_t st, u64 *partR, u64 *partC, i64 *nR, i64 *nC);
 int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR);
 int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
                      hipStream_t st);

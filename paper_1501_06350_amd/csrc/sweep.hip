@@ -1079,12 +1079,18 @@ int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hip
 // the block's entries are gathered into LDS with coalesced index reads, then each
 // lane folds one row.  Long rows are summed by segments first (k_pi_segments).
 //
-// The same row pull (REF = true) recomputes the fluid from the history, in double:
+// The same row pull recomputes the fluid from the history, in double (PM_REF):
 // F = F_0 + d P H - H, the fluid that equation HnFn assigns to H.  Float fluid gathers
 // a rounding error at every push; recomputing it restores the identity, so that
 // |F|_1 / (1-d) certifies |x - H|_1 again (Theorem 1).
+//
+// Over OUT instead of IN it is the adjoint sweep's pull (PM_ADJ): row j gathers the
+// snapshot d f_i of its out-neighbours i and adds (1/s_j) * sum_e snap_i w_e to F_j (the
+// transposed diffusion, see k_adj_pull; here lanes share the row and the order of the
+// additions is not the row order, so it is the fast adjoint, not the reproducible one).
 // ---------------------------------------------------------------------------
 constexpr int PI_WAVES = 4;
+constexpr int PM_PI = 0, PM_REF = 1, PM_ADJ = 2;
 
 struct PiArgs {
     const i64 *rb_start;
@@ -1104,20 +1110,22 @@ struct PiArgs {
     i64 n, nrb, nseg;
     int K;
     u64 *partR;
-    // fluid recomputation: ht = H / s (double), F_0, H, the fluid written
+    // fluid recomputation: ht = H / s (double), F_0, H, the fluid written;
+    // adjoint pull: ht = the snapshot, Fout = the adjoint fluid (read and written)
     const double *ht;
     const double *F0;
     const double *H;
     void *Fout;
 };
 
-// TX: type of the gathered x / s values; REF: fluid recomputation (always runs)
-template <typename TX, bool WTD, bool REF>
+// TX: type of the gathered values; MODE: PM_PI, PM_REF (always runs) or PM_ADJ
+template <typename TX, bool WTD, int MODE>
 __global__ void __launch_bounds__(256) k_pi_segments(PiArgs a) {
     __shared__ double red[256 / WAVE];
     DevCtl *ctl = a.ctl;
-    if (!REF && (ctl->done || ctl->sweep >= ctl->budget)) return;
-    const TX *xt = REF ? reinterpret_cast<const TX *>(a.ht) : reinterpret_cast<const TX *>(ctl->parity ? a.XT1 : a.XT0);
+    if (MODE != PM_REF && (ctl->done || ctl->sweep >= ctl->budget)) return;
+    const TX *xt = MODE != PM_PI ? reinterpret_cast<const TX *>(a.ht)
+                                 : reinterpret_cast<const TX *>(ctl->parity ? a.XT1 : a.XT0);
     const i64 sg = blockIdx.x;
     const i64 b = a.seg_b[sg], e = a.seg_e[sg];
     double acc = 0.0;
@@ -1145,10 +1153,12 @@ __global__ void __launch_bounds__(256) k_pi_segments(PiArgs a) {
     }
 }
 
-// T: type of x / s in power iteration, of the fluid in the recomputation (REF)
-template <typename T, bool WTD, bool REF>
+// T: type of x / s in power iteration, of the fluid in the recomputation (PM_REF);
+// the adjoint pull (PM_ADJ) is double throughout
+template <typename T, bool WTD, int MODE>
 __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
-    using TX = typename std::conditional<REF, double, T>::type;
+    constexpr bool REF = MODE == PM_REF, ADJ = MODE == PM_ADJ;
+    using TX = typename std::conditional<MODE != PM_PI, double, T>::type;
     __shared__ double tile[PI_WAVES][RB_NNZ];
     __shared__ u64 red[PSR * PI_WAVES];
     __shared__ int bad;
@@ -1156,8 +1166,10 @@ __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
     if (!REF && (ctl->done || ctl->sweep >= ctl->budget)) return;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
-    const int par = REF ? 0 : ctl->parity;
-    const TX *xt = REF ? reinterpret_cast<const TX *>(a.ht) : reinterpret_cast<const TX *>(par ? a.XT1 : a.XT0);
+    const int par = MODE != PM_PI ? 0 : ctl->parity;
+    const TX *xt = MODE != PM_PI ? reinterpret_cast<const TX *>(a.ht)
+                                 : reinterpret_cast<const TX *>(par ? a.XT1 : a.XT0);
+    u64 mx = 0;  // adjoint: largest |F| (as bits of a nonnegative double)
     T *xtn = reinterpret_cast<T *>(par ? a.XT0 : a.XT1);
     const double *x = par ? a.X1 : a.X0;
     double *xn = par ? a.X0 : a.X1;
@@ -1227,6 +1239,13 @@ __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
             if (REF) {
                 const double f = (a.F0[row] + a.d * acc) - a.H[row];
                 reinterpret_cast<T *>(a.Fout)[row] = (T)f;
+            } else if (ADJ) {
+                double *Fa = reinterpret_cast<double *>(a.Fout);
+                const double f = Fa[row] + a.inv_s[row] * acc;
+                Fa[row] = f;
+                if (!limbs_add_checked(R, fabs(f), a.K)) bad = 1;
+                const u64 b = (u64)__double_as_longlong(fabs(f));
+                mx = b > mx ? b : mx;
             } else {
                 const double y = a.d * acc + (a.Z ? (1.0 - a.d) * a.Z[row] : a.zc);
                 xn[row] = y;
@@ -1237,7 +1256,7 @@ __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
         wave_sync_lds();  // the next item reuses this wave's tile
     }
     if (REF) return;  // the residual of the recomputed fluid is summed by k_reduce_F
-    store_residual_partial(R, 0, red, a.partR + (i64)blockIdx.x * PSR);
+    store_residual_partial(R, mx, red, a.partR + (i64)blockIdx.x * PSR);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
 
@@ -1273,26 +1292,27 @@ static PiArgs make_pi_args(const DevGraph &g, const RowBlocks &rb, SolveState &s
     return a;
 }
 
-template <bool REF>
-static int launch_row_pull(PiArgs &a, const DevGraph &g, const RowBlocks &rb, int fp32, hipStream_t st) {
+// weighted: whether the pulled edges carry weights (a.in_w)
+template <int MODE>
+static int launch_row_pull(PiArgs &a, bool weighted, const RowBlocks &rb, int fp32, hipStream_t st) {
     if (rb.nseg > 0) {
         const unsigned gs = (unsigned)rb.nseg;
-        if (fp32 && !REF) {
-            if (g.weighted) k_pi_segments<float, true, REF><<<gs, 256, 0, st>>>(a);
-            else k_pi_segments<float, false, REF><<<gs, 256, 0, st>>>(a);
+        if (fp32 && MODE == PM_PI) {
+            if (weighted) k_pi_segments<float, true, MODE><<<gs, 256, 0, st>>>(a);
+            else k_pi_segments<float, false, MODE><<<gs, 256, 0, st>>>(a);
         } else {
-            if (g.weighted) k_pi_segments<double, true, REF><<<gs, 256, 0, st>>>(a);
-            else k_pi_segments<double, false, REF><<<gs, 256, 0, st>>>(a);
+            if (weighted) k_pi_segments<double, true, MODE><<<gs, 256, 0, st>>>(a);
+            else k_pi_segments<double, false, MODE><<<gs, 256, 0, st>>>(a);
         }
         DI_LAUNCH_CHECK();
     }
     const unsigned grid = grid_for(rb.nrb, PI_WAVES, PI_GRID);
-    if (fp32) {
-        if (g.weighted) k_pi_rows<float, true, REF><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
-        else k_pi_rows<float, false, REF><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+    if (fp32 && MODE != PM_ADJ) {
+        if (weighted) k_pi_rows<float, true, MODE><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+        else k_pi_rows<float, false, MODE><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
     } else {
-        if (g.weighted) k_pi_rows<double, true, REF><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
-        else k_pi_rows<double, false, REF><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+        if (weighted) k_pi_rows<double, true, MODE><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
+        else k_pi_rows<double, false, MODE><<<grid, PI_WAVES * WAVE, 0, st>>>(a);
     }
     DI_LAUNCH_CHECK();
     return DI_OK;
@@ -1301,7 +1321,7 @@ static int launch_row_pull(PiArgs &a, const DevGraph &g, const RowBlocks &rb, in
 int launch_pi_iteration(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, hipStream_t st) {
     PiArgs a = make_pi_args(g, rb, s, p);
     s.nR = grid_for(rb.nrb, PI_WAVES, PI_GRID);
-    return launch_row_pull<false>(a, g, rb, p.fp32, st);
+    return launch_row_pull<PM_PI>(a, g.weighted, rb, p.fp32, st);
 }
 
 __global__ void k_scaled_by_inv_s(const double *__restrict__ H, const double *__restrict__ inv_s, i64 n,
@@ -1319,7 +1339,7 @@ int launch_refine_fluid(const DevGraph &g, const RowBlocks &rb, SolveState &s, c
     a.F0 = s.F0;
     a.H = s.H;
     a.Fout = s.F;
-    return launch_row_pull<true>(a, g, rb, p.fp32, st);
+    return launch_row_pull<PM_REF>(a, g.weighted, rb, p.fp32, st);
 }
 
 __global__ void k_fill_bytes_zero(unsigned *p, i64 words) {
@@ -1532,6 +1552,36 @@ int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevC
     DI_LAUNCH_CHECK();
     *nR = gr;
     return DI_OK;
+}
+
+int launch_adj_sweep_fast(const DevGraph &g, const RowBlocks &rb_out, double *F, double *H, double *snap, DevCtl *ctl,
+                          const SweepParams &p, hipStream_t st, u64 *partR, u64 *partC, i64 *nR, i64 *nC) {
+    const unsigned gs = grid_for(g.n, 256, SNAP_GRID);
+    k_adj_snapshot<<<gs, 256, 0, st>>>(F, H, snap, g.in_ptr, g.n, p.d, ctl, partC);
+    DI_LAUNCH_CHECK();
+    *nC = gs;
+    PiArgs a{};
+    a.rb_start = rb_out.start;
+    a.seg_first = rb_out.seg_first;
+    a.seg_count = rb_out.seg_count;
+    a.seg_b = rb_out.seg_b;
+    a.seg_e = rb_out.seg_e;
+    a.partial = rb_out.partial;
+    a.in_ptr = g.out_ptr;  // the pull walks OUT rows
+    a.in_idx = g.out_idx;
+    a.in_w = g.w;
+    a.inv_s = g.inv_s;
+    a.ctl = ctl;
+    a.d = p.d;
+    a.n = g.n;
+    a.nrb = rb_out.nrb;
+    a.nseg = rb_out.nseg;
+    a.K = p.K;
+    a.partR = partR;
+    a.ht = snap;
+    a.Fout = F;
+    *nR = grid_for(rb_out.nrb, PI_WAVES, PI_GRID);
+    return launch_row_pull<PM_ADJ>(a, g.weighted, rb_out, 0, st);
 }
 
 int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR) {
