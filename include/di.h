@@ -166,6 +166,9 @@ int di_power(di_ctx *ctx, double tol, di_stats *st);
  *           mu_j = sum over j's out-edges e' of P_{e'} lambda_{target(e')}
  * with x the raw history H of the last di_diffuse.  g, dZ (n doubles) and dw (m
  * doubles, may be NULL) are host arrays (on_device = 0) or device arrays (1).
+ * Each sweep snapshots the active fluid and pulls it over OUT rows; a deterministic
+ * context adds in row order (bit-reproducible), any other context sums a row across a
+ * wave (faster, reproducible only to rounding).
  * Requires a converged di_diffuse (DI_ESTATE otherwise); k = 1, single graph.
  */
 int di_adjoint(di_ctx *ctx, const double *g, double tol_inf, double *dZ, double *dw, int on_device, di_stats *st);
