@@ -4,8 +4,8 @@ webgen(1M, 2): the library's D-Iteration and power iteration against the oracle'
 synchronous D-Iteration run to a certified 1e-11, element by element (|dx|_1 <= 1e-9 |x|_1
 with double arithmetic, <= 1e-6 |x|_1 with float fluid or float x/s).
 
-webgen(50M, 3), the headline configuration (float fluid, double history, default options,
-tol 1e-8): the oracle recomputes, in double, the exact residual F = F_0 + d P H - H of the
+webgen(50M, 3), the headline configuration (default options, tol 1e-8, double fluid and
+float fluid): the oracle recomputes, in double, the exact residual F = F_0 + d P H - H of the
 history the library returns, over all rows and row by row on a sample, and checks the
 certificate |x - H|_1 <= |F|_1 / (1-d) <= tol (Theorem 1) without the library's own residual;
 power iteration with double x/s must land within the two certified bounds of it.
@@ -58,33 +58,45 @@ def exact_residual_l1(og, F0, H):
     return float(np.abs(F0 + D * og.P_times(H) - H).sum())
 
 
-def test_headline_50m_certificate(gpu):
+@pytest.fixture(scope="module")
+def web50m():
     g = W.webgen(50_000_000, 3)
-    say("webgen(50M, 3): n=%d m=%d" % (g.n, g.m))
+    return g, O.OGraph.of(g)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_headline_50m_certificate(gpu, web50m, fp32):
+    g, og = web50m
+    say("webgen(50M, 3): n=%d m=%d, float fluid %d" % (g.n, g.m, fp32))
     Z = O.uniform_Z(g.n)
     F0 = (1 - D) * Z
-    with gpu.from_graph(g, d=D, fluid_fp32=True) as s:
+    with gpu.from_graph(g, d=D, fluid_fp32=fp32) as s:
         st = s.diffuse(1e-8)
         assert st["converged"] and st["bound"] <= 1e-8
         H = s.read(gpu.H)
         Fg = s.read(gpu.F)
     say("DI: %d sweeps, bound %.3e" % (st["sweeps"], st["bound"]))
     assert np.all(H >= 0)
-    og = O.OGraph.of(g)
     # every row: the certificate from the oracle's own residual
     R = exact_residual_l1(og, F0, H)
     say("oracle residual |F|_1 / (1-d) = %.4e" % (R / (1 - D)))
     assert R / (1 - D) <= 1e-8 * (1 + 1e-6)
-    # row by row on a sample: the fluid the library returns is that residual (rounded to float)
-    # (the two sides sum a row's terms in different orders: allow the rounding of a sum of
-    # in-degree + 2 nonnegative terms, then the float rounding of the result)
+    # row by row on a sample: the fluid the library returns is that residual.  Float fluid
+    # was recomputed from H at the end: the two sides sum a row's terms in different orders
+    # (allow the rounding of a sum of in-degree + 2 nonnegative terms), then the result was
+    # rounded to float.  Double fluid was never recomputed: it carries the rounding of the
+    # pushes it received (far below 1e-11 of the row's terms).
     rows = np.sort(np.random.default_rng(5).choice(g.n, size=4096, replace=False))
     PH = og.P_times_rows(rows, H)
     Fr = F0[rows] + D * PH - H[rows]
-    indeg = (og.in_ptr[rows + 1] - og.in_ptr[rows]).astype(np.float64)
-    sums = (indeg + 3) * 2.0 ** -52 * (F0[rows] + D * PH + H[rows])
+    terms = F0[rows] + D * PH + H[rows]
     gap = np.abs(Fg[rows] - Fr)
-    assert np.all(gap <= np.abs(Fr) * 2.0 ** -23 + sums), float(np.max(gap - np.abs(Fr) * 2.0 ** -23 - sums))
+    if fp32:
+        indeg = (og.in_ptr[rows + 1] - og.in_ptr[rows]).astype(np.float64)
+        allow = np.abs(Fr) * 2.0 ** -23 + (indeg + 3) * 2.0 ** -52 * terms
+    else:
+        allow = 1e-11 * terms
+    assert np.all(gap <= allow), float(np.max(gap - allow))
     # power iteration with double x/s on the same graph
     with gpu.from_graph(g, d=D, fluid_fp32=False) as s64:
         p = s64.power(1e-8)
