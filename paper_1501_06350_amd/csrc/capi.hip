@@ -1119,8 +1119,12 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     double *ddZ = dZ, *ddw = dw;
     double *tZ = nullptr, *tw = nullptr;
     if (!on_device) {
-        DI_HIP(hipMalloc((void **)&tZ, sizeof(double) * n));
-        if (dw) DI_HIP(hipMalloc((void **)&tw, sizeof(double) * std::max<i64>(c->g.m, 1)));
+        const bool ok = hipMalloc((void **)&tZ, sizeof(double) * n) == hipSuccess &&
+                        (!dw || hipMalloc((void **)&tw, sizeof(double) * std::max<i64>(c->g.m, 1)) == hipSuccess);
+        if (!ok) {
+            if (tZ) (void)hipFree(tZ);
+            DI_FAIL(DI_ENOMEM, "device allocation for the gradients failed");
+        }
         ddZ = tZ;
         ddw = dw ? tw : nullptr;
     }
