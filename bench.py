@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--range-log2", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=0)
     ap.add_argument("--theta", type=float, default=1.0)
+    ap.add_argument("--range-cut", type=int, default=0, help="range_cut option (-1: ranges at multiples of 2^rb)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a copy of known size, then one DI solve")
     ap.add_argument("--batched-only", action="store_true",
@@ -147,7 +148,8 @@ def main():
     g = W.webgen(args.n, args.seed)
     n, m = g.n, g.m
     log("graph webgen(n=%d, seed=%d): m=%d generated in %.1fs" % (n, args.seed, m, time.time() - t0))
-    opts = dict(timing=True, range_log2=args.range_log2, inner_rounds=args.rounds, theta=args.theta)
+    opts = dict(timing=True, range_log2=args.range_log2, inner_rounds=args.rounds, theta=args.theta,
+                range_cut=args.range_cut)
 
     # headline: D-Iteration in the chosen fluid precision, then power iteration with double
     # x/s on a double context (its certificate holds for exact iterates; float x/s carries
@@ -159,9 +161,11 @@ def main():
     di = time_di(s, args.steps, args.warmup, n, m)
     xd = s.read(B.H)
     used_rb, used_rounds = s.info(B.INFO_RANGE_LOG2), s.info(B.INFO_INNER_ROUNDS)
-    if fp32:
-        s.close()
-        s = B.from_graph(g, d=D, fluid_fp32=False, timing=True)
+    n_internal = s.info(B.INFO_N_INTERNAL)
+    s.close()
+    # power iteration on the caller's numbering (cut-aligned ranges only serve the sweeps;
+    # their padding rows would slow the row pull down)
+    s = B.from_graph(g, d=D, fluid_fp32=False, timing=True, range_cut=-1)
     pi = time_pi(s, args.steps, n, m)
     s.close()
     di_pi_l1 = float(np.abs(xd - pi.pop("x")).sum())
@@ -182,7 +186,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "webgen n=%d m=%d seed=%d, d=0.85, uniform Z, L1 tol 1e-8, %s fluid + f64 history" %
                                (n, m, args.seed, "f32" if fp32 else "f64"),
-                   "range_log2": used_rb, "inner_rounds": used_rounds, "theta": args.theta},
+                   "range_log2": used_rb, "inner_rounds": used_rounds, "theta": args.theta,
+                   "range_cut": args.range_cut, "internal_nodes": n_internal},
         "time_to_tol_ms": {"di": round(di["ms"], 3), "pi": round(pi["ms"], 3)},
         "di_vs_pi_speedup": round(pi["ms"] / di["ms"], 3),
         "di": {"sweeps": di["sweeps"], "edge_updates": di["edges"], "diffusions": di["diffusions"],
@@ -201,8 +206,12 @@ def main():
         s2 = B.from_graph(g, d=D, fluid_fp32=not fp32, **opts)
         d2 = time_di(s2, args.steps, args.warmup, n, m)
         x2 = s2.read(B.H)
-        p2 = time_pi(s2, args.steps, n, m) if not fp32 else None
         s2.close()
+        p2 = None
+        if not fp32:
+            s2 = B.from_graph(g, d=D, fluid_fp32=True, timing=True, range_cut=-1)
+            p2 = time_pi(s2, args.steps, n, m)
+            s2.close()
         leg = {"ms": round(d2["ms"], 3), "sweeps": d2["sweeps"], "edge_updates": d2["edges"],
                "geups": round(d2["geups"], 3), "bound": d2["bound"],
                "l1_diff_to_headline_di": float(np.abs(x2 - xd).sum()),
@@ -241,9 +250,14 @@ def traffic_profile(prec):
 
 
 def sweep_source_hash():
+    """Hash of the library sources that decide the sweep's memory traffic (the kernel, the
+    graph layout and split, the API that chooses them)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1501_06350_amd", "csrc", "sweep.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("sweep.hip", "sweep.h", "graph.hip", "capi.hip"):
+        with open(os.path.join(ROOT, "paper_1501_06350_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(prec):
@@ -258,7 +272,7 @@ def measured_traffic(prec):
         if ":" in line and line.startswith("- "):
             key, val = line[2:].split(":", 1)
             vals[key.strip()] = val.strip().strip("`")
-    if vals.get("sweep.hip sha256") != sweep_source_hash():
+    if vals.get("source sha256") != sweep_source_hash():
         return None
     try:
         return float(vals["traffic bytes per launch"])
@@ -281,7 +295,7 @@ def traffic_probe(args, fp32):
     with B.from_graph(g, d=D, fluid_fp32=fp32) as s:
         st = s.diffuse(TOL)
     torch.cuda.synchronize()
-    log("traffic probe: copies of %d bytes, then %d sweeps, sweep.hip sha256 %s" %
+    log("traffic probe: copies of %d bytes, then %d sweeps, source sha256 %s" %
         (COPY_BYTES, st["sweeps"], sweep_source_hash()))
 
 

@@ -95,6 +95,15 @@ typedef struct {
  *                    keep the summed device time (di_info DI_INFO_KERNEL_NS) [0]
  *   normalized_stop: 1 = stop on |F|_1 / (1 - d - d l/|Z|_1) instead of |F|_1 / (1-d)
  *                    (implicit completion, Section 3.3) [0]
+ *   range_cut      : one right-hand side on one graph with fast sweeps: a block-local
+ *                    range may end up to range_cut nodes before its 2^range_log2 slots
+ *                    are full, at the boundary crossed by the fewest edges shorter than a
+ *                    range (on a host-ordered web graph, between two hosts); its unused
+ *                    slots become padding nodes without edges or fluid.  The internal
+ *                    numbering keeps the caller's order (edges, rows and results are
+ *                    mapped back), so every call behaves as on the caller's graph.
+ *                    0 = auto (2^range_log2 / 2), -1 = ranges at multiples of
+ *                    2^range_log2 (no padding) [0]
  *   stream         : hipStream_t to run on; NULL = the null stream
  */
 typedef struct {
@@ -111,6 +120,7 @@ typedef struct {
     int sweeps_per_sync;
     int normalized_stop;
     int timing;
+    int range_cut;
     void *stream;
 } di_opts;
 

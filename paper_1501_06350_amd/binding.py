@@ -44,7 +44,7 @@ class DiOpts(ctypes.Structure):
                 ("deterministic", ctypes.c_int), ("range_log2", ctypes.c_int), ("inner_rounds", ctypes.c_int),
                 ("k", ctypes.c_int), ("n_graphs", ctypes.c_int64), ("graph_ptr", ctypes.c_void_p),
                 ("loop_mode", ctypes.c_int), ("sweeps_per_sync", ctypes.c_int), ("normalized_stop", ctypes.c_int),
-                ("timing", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("timing", ctypes.c_int), ("range_cut", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class DiStats(ctypes.Structure):
@@ -130,7 +130,8 @@ class Solver:
     def __init__(self, n, out_ptr, out_idx, w=None, d: float = 0.85, Z=None, *, fluid_fp32: bool = False,
                  theta: float = 1.0, max_sweeps: int = 0, deterministic: bool = False, range_log2: int = 0,
                  inner_rounds: int = 0, k: int = 1, graph_ptr=None, loop_mode: int = LOOP_STREAM,
-                 sweeps_per_sync: int = 0, normalized_stop: bool = False, timing: bool = False, stream=None):
+                 sweeps_per_sync: int = 0, normalized_stop: bool = False, timing: bool = False, range_cut: int = 0,
+                 stream=None):
         lib = load_library()
         self._lib = lib
         self.n = int(n)
@@ -162,6 +163,7 @@ class Solver:
         opts.sweeps_per_sync = int(sweeps_per_sync)
         opts.normalized_stop = int(normalized_stop)
         opts.timing = int(timing)
+        opts.range_cut = int(range_cut)
         if stream is None:
             stream = current_stream_handle()
         opts.stream = ctypes.c_void_p(stream) if stream else None

@@ -55,6 +55,11 @@ struct di_ctx {
     double *d_gscale = nullptr;
     std::vector<GraphCtl> h_gctl;
     std::vector<GraphInfo> h_ginfo;
+    // one graph with cut-aligned ranges: range r holds caller nodes [seg_start[r],
+    // seg_start[r+1]) at internal nodes r 2^rb + 0, 1, ...; the rest of its slots are padding
+    bool seg = false;
+    int seg_rb = 0;
+    std::vector<i64> seg_start;
     int rounds = 8;
     int spc = 8;  // sweeps per host check
     double zsum = 1.0;  // sum of Z (single right-hand side)
@@ -348,6 +353,185 @@ int fill_stats_mg(di_ctx *c, di_stats *st, const DevCtl &h, const DevCtl &before
     return DI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Cut-aligned ranges (one graph, one right-hand side, fast sweeps).  lcut(p) counts the
+// edges shorter than a range that cross the boundary between nodes p-1 and p; a range that
+// starts at caller node s ends at the p in (s + B - X, s + B] with the smallest lcut (the
+// largest such p on ties), and its slots past p - s are padding.  The relabelling is
+// monotone, so rows stay sorted, IN keeps its order, and OUT keeps its edge order.
+// ---------------------------------------------------------------------------
+__global__ void k_short_crossings(const i64 *__restrict__ ptr, const int *__restrict__ idx, i64 n, i64 B,
+                                  unsigned long long *diff) {
+    for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x) {
+        for (i64 e = ptr[u]; e < ptr[u + 1]; ++e) {
+            const i64 v = idx[e];
+            const i64 lo = v < u ? v : u, hi = v < u ? u : v;
+            if (hi != lo && hi - lo < B) {
+                atomicAdd(&diff[lo + 1], 1ull);
+                atomicAdd(&diff[hi + 1], ~0ull);  // -1 modulo 2^64
+            }
+        }
+    }
+}
+
+// internal row pointer: slot j of range r is caller node start[r] + j, or padding (an
+// empty row at the end of the range's edges)
+__global__ void k_pad_rows(const i64 *__restrict__ ptr, const i64 *__restrict__ start, i64 nr, int rb, i64 n_int,
+                           i64 m, i64 *pptr) {
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q <= n_int; q += (i64)gridDim.x * blockDim.x) {
+        if (q == n_int) {
+            pptr[q] = m;
+            continue;
+        }
+        const i64 r = q >> rb, j = q & (((i64)1 << rb) - 1), len = start[r + 1] - start[r];
+        pptr[q] = ptr[start[r] + (j < len ? j : len)];
+    }
+}
+
+// targets to internal numbers; coarse[t] = the range holding caller node t << cs (every
+// range holds at least 2^cs caller nodes, so the walk takes at most two steps)
+__global__ void k_relabel(int *idx, i64 m, const i64 *__restrict__ start, const int *__restrict__ coarse, int cs,
+                          int rb) {
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (i64)gridDim.x * blockDim.x) {
+        const i64 u = idx[e];
+        i64 r = coarse[u >> cs];
+        while (start[r + 1] <= u) ++r;
+        idx[e] = (int)((r << rb) + (u - start[r]));
+    }
+}
+
+// Upload OUT in the internal numbering of cut-aligned ranges.  Sets c->seg, c->seg_start and
+// c->g.n; returns DI_OK with c->seg = false when no range would end early.
+int upload_segmented(di_ctx *c, const i64 *ptr, const int *idx, const float *w, i64 n, i64 m, int rb, i64 X) {
+    const i64 B = (i64)1 << rb;
+    i64 *d_ptr = nullptr;
+    int *d_idx = nullptr;
+    unsigned long long *diff = nullptr;
+    i64 *excl = nullptr, *temp = nullptr;
+    auto cleanup = [&]() {
+        for (void *q : {(void *)d_ptr, (void *)diff, (void *)excl, (void *)temp})
+            if (q) (void)hipFree(q);
+    };
+    auto hip_ok = [&](hipError_t e) {
+        if (e == hipSuccess) return true;
+        set_error("cut-aligned range layout: %s", hipGetErrorString(e));
+        return false;
+    };
+    if (!hip_ok(hipMalloc((void **)&d_ptr, sizeof(i64) * (n + 1))) ||
+        !hip_ok(hipMalloc((void **)&d_idx, sizeof(int) * std::max<i64>(m, 1))) ||
+        !hip_ok(hipMalloc((void **)&diff, sizeof(i64) * (n + 2))) ||
+        !hip_ok(hipMalloc((void **)&excl, sizeof(i64) * (n + 2))) ||
+        !hip_ok(hipMalloc((void **)&temp, sizeof(i64) * (scan_temp_elems(n + 2) + 64))) ||
+        !hip_ok(hipMemcpy(d_ptr, ptr, sizeof(i64) * (n + 1), hipMemcpyHostToDevice)) ||
+        (m && !hip_ok(hipMemcpy(d_idx, idx, sizeof(int) * m, hipMemcpyHostToDevice)))) {
+        cleanup();
+        if (d_idx) (void)hipFree(d_idx);
+        return DI_EHIP;
+    }
+    c->g.out_idx = d_idx;  // owned by the context from here on
+    int rc = launch_fill_zero(diff, sizeof(i64) * (n + 2), c->st);
+    if (rc == DI_OK) {
+        k_short_crossings<<<grid_for(n, 256, 16384), 256, 0, c->st>>>(d_ptr, d_idx, n, B, diff);
+        if (hipGetLastError() != hipSuccess) rc = DI_EHIP;
+    }
+    // lcut(p) = sum of diff[0..p] = the exclusive scan at p + 1
+    if (rc == DI_OK) rc = scan_exclusive(reinterpret_cast<const i64 *>(diff), excl, n + 2, temp, c->st);
+    std::vector<i64> lcut((size_t)n + 2);
+    if (rc == DI_OK && !hip_ok(hipMemcpyAsync(lcut.data(), excl, sizeof(i64) * (n + 2), hipMemcpyDeviceToHost, c->st)))
+        rc = DI_EHIP;
+    if (rc == DI_OK && !hip_ok(hipStreamSynchronize(c->st))) rc = DI_EHIP;
+    if (rc != DI_OK) {
+        cleanup();
+        return rc;
+    }
+    std::vector<i64> start{0};
+    for (i64 s = 0; n - s > B;) {
+        i64 best = s + B;
+        for (i64 p = s + B; p > s + B - X; --p)
+            if (lcut[p + 1] < lcut[best + 1]) best = p;
+        start.push_back(best);
+        s = best;
+    }
+    start.push_back(n);
+    const i64 nr = (i64)start.size() - 1;
+    if (nr == (n + B - 1) / B) {  // every range full: the plain layout (OUT as uploaded)
+        c->g.out_ptr = d_ptr;
+        d_ptr = nullptr;
+        cleanup();
+        return DI_OK;
+    }
+    const i64 n_int = (nr - 1) * B + (n - start[nr - 1]);
+    if (n_int >= 0x7fffffffll) {
+        cleanup();
+        set_error("cut-aligned ranges need more than 2^31 - 1 internal nodes; use range_cut = -1");
+        return DI_EINVAL;
+    }
+    const int cs = rb - 1;  // every range holds more than B - X >= B / 2 caller nodes
+    std::vector<int> coarse((size_t)((n - 1) >> cs) + 1);
+    for (i64 r = 0, t = 0; t < (i64)coarse.size(); ++t) {
+        while (start[r + 1] <= (t << cs)) ++r;
+        coarse[t] = (int)r;
+    }
+    i64 *d_start = nullptr;
+    int *d_coarse = nullptr;
+    i64 *pptr = nullptr;
+    if (!hip_ok(hipMalloc((void **)&d_start, sizeof(i64) * (nr + 1))) ||
+        !hip_ok(hipMalloc((void **)&d_coarse, sizeof(int) * coarse.size())) ||
+        !hip_ok(hipMalloc((void **)&pptr, sizeof(i64) * (n_int + 1))) ||
+        !hip_ok(hipMemcpy(d_start, start.data(), sizeof(i64) * (nr + 1), hipMemcpyHostToDevice)) ||
+        !hip_ok(hipMemcpy(d_coarse, coarse.data(), sizeof(int) * coarse.size(), hipMemcpyHostToDevice))) {
+        for (void *q : {(void *)d_start, (void *)d_coarse, (void *)pptr})
+            if (q) (void)hipFree(q);
+        cleanup();
+        return DI_EHIP;
+    }
+    k_pad_rows<<<grid_for(n_int + 1, 256, 16384), 256, 0, c->st>>>(d_ptr, d_start, nr, rb, n_int, m, pptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && m) {
+        k_relabel<<<grid_for(m, 256, 16384), 256, 0, c->st>>>(d_idx, m, d_start, d_coarse, cs, rb);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    (void)hipFree(d_start);
+    (void)hipFree(d_coarse);
+    cleanup();
+    if (!hip_ok(e)) {
+        (void)hipFree(pptr);
+        return DI_EHIP;
+    }
+    c->g.out_ptr = pptr;
+    c->g.n = n_int;
+    c->seg = true;
+    c->seg_rb = rb;
+    c->seg_start = std::move(start);
+    (void)w;
+    return DI_OK;
+}
+
+// caller array (n_user values) -> internal layout (padding gets fill)
+void seg_expand(const di_ctx *c, const double *src, double *dst, double fill) {
+    const i64 B = (i64)1 << c->seg_rb, nr = (i64)c->seg_start.size() - 1;
+    for (i64 r = 0; r < nr; ++r) {
+        const i64 s = c->seg_start[r], len = c->seg_start[r + 1] - s;
+        for (i64 j = 0; j < B && r * B + j < c->g.n; ++j) dst[r * B + j] = j < len ? src[s + j] : fill;
+    }
+}
+
+// internal layout -> caller array
+template <typename T>
+void seg_compact(const di_ctx *c, const T *src, T *dst) {
+    const i64 B = (i64)1 << c->seg_rb, nr = (i64)c->seg_start.size() - 1;
+    for (i64 r = 0; r < nr; ++r) {
+        const i64 s = c->seg_start[r], len = c->seg_start[r + 1] - s;
+        for (i64 j = 0; j < len; ++j) dst[s + j] = src[r * B + j];
+    }
+}
+
+// caller node of internal (real) node q
+inline i64 seg_user(const di_ctx *c, i64 q) {
+    return c->seg_start[q >> c->seg_rb] + (q & (((i64)1 << c->seg_rb) - 1));
+}
+
 }  // namespace
 
 extern "C" {
@@ -408,6 +592,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     if (opt.inner_rounds < 0 || opt.inner_rounds > 64) DI_FAIL(DI_EINVAL, "inner_rounds must be in 0..64");
     if (opt.loop_mode != DI_LOOP_STREAM && opt.loop_mode != DI_LOOP_GRAPH) DI_FAIL(DI_EINVAL, "bad loop_mode");
     if (opt.sweeps_per_sync < 0) DI_FAIL(DI_EINVAL, "sweeps_per_sync must be >= 0");
+    if (opt.range_cut < -1) DI_FAIL(DI_EINVAL, "range_cut must be -1, 0 or positive");
     i64 n = g->n;
     const i64 m = g->m;
     if (opt.n_graphs > 1) {
@@ -555,14 +740,34 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         return fail(DI_ENOMEM);
     }
 
-    // upload OUT
-    if ((rc = dalloc(c, &c->g.out_ptr, n + 1)) || (rc = dalloc(c, &c->g.out_idx, m))) return fail(rc);
-    if (w && (rc = dalloc(c, &c->g.w, m))) return fail(rc);
-    if (hipMemcpy(c->g.out_ptr, ptr, sizeof(i64) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        (m && hipMemcpy(c->g.out_idx, idx, sizeof(int) * m, hipMemcpyHostToDevice) != hipSuccess) ||
-        (w && m && hipMemcpy(c->g.w, w, sizeof(float) * m, hipMemcpyHostToDevice) != hipSuccess)) {
-        set_error("upload of the graph failed");
-        return fail(DI_EHIP);
+    // upload OUT (for one graph with fast sweeps, in the numbering of cut-aligned ranges)
+    const i64 B = (i64)1 << rb;
+    std::vector<double> segz;
+    if (k == 1 && opt.n_graphs == 1 && !opt.deterministic && opt.range_cut >= 0 && n > B) {
+        const i64 X = opt.range_cut == 0 ? B / 2 : std::min<i64>(opt.range_cut, B / 2);
+        if ((rc = upload_segmented(c, ptr, idx, w, n, m, rb, X)) != DI_OK) return fail(rc);
+        if (w && (rc = dalloc(c, &c->g.w, m))) return fail(rc);
+        if (w && m && hipMemcpy(c->g.w, w, sizeof(float) * m, hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("upload of the weights failed");
+            return fail(DI_EHIP);
+        }
+        if (c->seg) {  // Z in the internal layout (padding nodes get none)
+            n = c->g.n;
+            std::vector<double> zu;
+            if (!Z) zu.assign((size_t)n_user, 1.0 / (double)n_user);
+            segz.assign((size_t)n, 0.0);
+            seg_expand(c, Z ? Z : zu.data(), segz.data(), 0.0);
+            Z = segz.data();
+        }
+    } else {
+        if ((rc = dalloc(c, &c->g.out_ptr, n + 1)) || (rc = dalloc(c, &c->g.out_idx, m))) return fail(rc);
+        if (w && (rc = dalloc(c, &c->g.w, m))) return fail(rc);
+        if (hipMemcpy(c->g.out_ptr, ptr, sizeof(i64) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+            (m && hipMemcpy(c->g.out_idx, idx, sizeof(int) * m, hipMemcpyHostToDevice) != hipSuccess) ||
+            (w && m && hipMemcpy(c->g.w, w, sizeof(float) * m, hipMemcpyHostToDevice) != hipSuccess)) {
+            set_error("upload of the graph failed");
+            return fail(DI_EHIP);
+        }
     }
 
     c->rounds = opt.inner_rounds ? opt.inner_rounds : 4;
@@ -707,9 +912,15 @@ int di_set_z(di_ctx *c, const double *Z) {
             }
             if (!(gz[q] > 0.0)) DI_FAIL(DI_EINVAL, "Z sums to zero on graph %lld", (long long)q);
         }
+    } else if (c->seg) {  // cut-aligned ranges: padding nodes get no Z
+        std::vector<double> zu;
+        if (!Z) zu.assign((size_t)nu, 1.0 / (double)nu);
+        seg_expand(c, Z ? Z : zu.data(), f0.data(), 0.0);
     } else {
         for (i64 i = 0; i < n; ++i) f0[i] = Z ? Z[i] : 1.0 / (double)n;
     }
+    std::vector<double> zint;  // Z in the internal layout, for power iteration
+    if (c->seg) zint = f0;
     double zsum = 0.0, mx = 0.0;
     for (i64 i = 0; i < n; ++i) {
         zsum += f0[i];
@@ -717,9 +928,9 @@ int di_set_z(di_ctx *c, const double *Z) {
         mx = std::max(mx, std::fabs(c->p.fp32 ? (double)(float)f0[i] : f0[i]));
     }
     if (c->n_graphs == 1) {  // power iteration reads Z
-        if (Z) {
+        if (Z || c->seg) {
             if (!c->s.Z) DI_TRY(dalloc(c, &c->s.Z, n));
-            DI_HIP(hipMemcpy(c->s.Z, Z, sizeof(double) * n, hipMemcpyHostToDevice));
+            DI_HIP(hipMemcpy(c->s.Z, c->seg ? zint.data() : Z, sizeof(double) * n, hipMemcpyHostToDevice));
         } else if (c->s.Z) {
             (void)hipFree(c->s.Z);
             c->s.Z = nullptr;
@@ -904,6 +1115,85 @@ int copy_small(const void *src, size_t bytes, void *dst, int on_device) {
 }
 
 // di_read for a union of graphs: vectors come back in the caller's numbering.
+// Reads of node-indexed values and of IN under cut-aligned ranges: the internal array is
+// brought to the host and put back in the caller's numbering.  Returns 1 when `what` is
+// not one of these (the caller reads it as usual).
+int read_seg(di_ctx *c, int what, void *dst, int on_device, int *rc_out) {
+    const i64 n = c->g.n, nu = c->n_user, m = c->g.m;
+    auto put = [&](const void *src, size_t bytes) -> int {
+        if (on_device) DI_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+        else std::memcpy(dst, src, bytes);
+        return DI_OK;
+    };
+    auto doubles = [&](const double *dsrc, double scale) -> int {
+        std::vector<double> v((size_t)n), out((size_t)nu);
+        DI_HIP(hipMemcpy(v.data(), dsrc, sizeof(double) * n, hipMemcpyDeviceToHost));
+        seg_compact(c, v.data(), out.data());
+        if (scale != 1.0)
+            for (double &x : out) x *= scale;
+        return put(out.data(), sizeof(double) * nu);
+    };
+    switch (what) {
+    case DI_X_RAW:
+    case DI_H:
+        *rc_out = doubles(c->s.H, 1.0);
+        return 0;
+    case DI_X_NORM: {
+        DI_TRY(sync_ctl(c, c->s.ctl));
+        const double l = host_limbs(c->h_ctl->limbsL, c->p.K);
+        *rc_out = doubles(c->s.H, (1.0 - c->d) / (1.0 - c->d - c->d * l / c->zsum));
+        return 0;
+    }
+    case DI_F: {
+        if (!c->p.fp32) {
+            *rc_out = doubles(static_cast<const double *>(c->s.F), 1.0);
+            return 0;
+        }
+        std::vector<float> v((size_t)n);
+        std::vector<double> out((size_t)nu);
+        DI_HIP(hipMemcpy(v.data(), c->s.F, sizeof(float) * n, hipMemcpyDeviceToHost));
+        std::vector<float> vc((size_t)nu);
+        seg_compact(c, v.data(), vc.data());
+        for (i64 i = 0; i < nu; ++i) out[i] = (double)vc[i];
+        *rc_out = put(out.data(), sizeof(double) * nu);
+        return 0;
+    }
+    case DI_LAMBDA:
+        if (!c->lam) DI_FAIL(DI_ESTATE, "no adjoint has been computed");
+        *rc_out = doubles(c->lam, 1.0);
+        return 0;
+    case DI_X_PI:
+        if (!c->pi_done) DI_FAIL(DI_ESTATE, "di_power has not run for the current Z");
+        DI_TRY(sync_ctl(c, c->s.pctl));
+        *rc_out = doubles(c->s.X[c->h_ctl->parity], 1.0);
+        return 0;
+    case DI_INV_S:
+        *rc_out = doubles(c->g.inv_s, 1.0);
+        return 0;
+    case DI_IN_PTR: {
+        std::vector<i64> v((size_t)n + 1), out((size_t)nu + 1);
+        DI_HIP(hipMemcpy(v.data(), c->g.in_ptr, sizeof(i64) * (n + 1), hipMemcpyDeviceToHost));
+        seg_compact(c, v.data(), out.data());
+        out[nu] = m;
+        *rc_out = put(out.data(), sizeof(i64) * (nu + 1));
+        return 0;
+    }
+    case DI_IN_IDX: {
+        if (m == 0) {
+            *rc_out = DI_OK;
+            return 0;
+        }
+        std::vector<int> v((size_t)m);
+        DI_HIP(hipMemcpy(v.data(), c->g.in_idx, sizeof(int) * m, hipMemcpyDeviceToHost));
+        for (int &q : v) q = (int)seg_user(c, q);
+        *rc_out = put(v.data(), sizeof(int) * m);
+        return 0;
+    }
+    default:
+        return 1;
+    }
+}
+
 int read_union(di_ctx *c, int what, void *dst, int on_device) {
     const i64 G = c->n_graphs, nu = c->n_user;
     switch (what) {
@@ -975,6 +1265,11 @@ int di_read(di_ctx *c, int what, void *dst, int on_device) {
     if (!dst) DI_FAIL(DI_EINVAL, "dst is NULL");
     if (c->b) return read_batch(c->b, c->g, c->p, what, dst, on_device, c->st);
     if (c->s.range_graph) return read_union(c, what, dst, on_device);
+    if (c->seg) {
+        int rc = DI_OK;
+        const int h = read_seg(c, what, dst, on_device, &rc);
+        if (h != 1) return h == 0 ? rc : h;  // handled, or an error
+    }
     const i64 n = c->g.n, m = c->g.m;
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     auto copy_out = [&](const void *src, size_t bytes) -> int {
@@ -1066,18 +1361,24 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         DI_TRY(dalloc(c, &c->asnap, n));
         DI_TRY(dalloc(c, &c->actl, 1));
     }
-    std::vector<double> hg;
+    const i64 nu = c->n_user;  // the caller's node count (n is internal)
+    std::vector<double> hg, gint;
     const double *gsrc = g;
     double mx = 0.0;
     {
         if (on_device) {
-            hg.resize((size_t)n);
-            DI_HIP(hipMemcpy(hg.data(), g, sizeof(double) * n, hipMemcpyDeviceToHost));
+            hg.resize((size_t)nu);
+            DI_HIP(hipMemcpy(hg.data(), g, sizeof(double) * nu, hipMemcpyDeviceToHost));
             gsrc = hg.data();
         }
-        for (i64 i = 0; i < n; ++i) {
+        for (i64 i = 0; i < nu; ++i) {
             if (!std::isfinite(gsrc[i])) DI_FAIL(DI_EINVAL, "g[%lld] is not finite", (long long)i);
             mx = std::max(mx, std::fabs(gsrc[i]));
+        }
+        if (c->seg) {  // internal layout: padding nodes get no g
+            gint.assign((size_t)n, 0.0);
+            seg_expand(c, gsrc, gint.data(), 0.0);
+            gsrc = gint.data();
         }
     }
     SweepParams ap = c->p;
@@ -1116,29 +1417,46 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         if (h.done || h.overflow || h.sweep >= h.budget) break;
     }
     // gradients from x = H (forward history) and lambda
+    // (dZ goes through an internal-layout buffer for host outputs and cut-aligned ranges;
+    // dw keeps the caller's edge order in every layout)
     double *ddZ = dZ, *ddw = dw;
     double *tZ = nullptr, *tw = nullptr;
-    if (!on_device) {
-        const bool ok = hipMalloc((void **)&tZ, sizeof(double) * n) == hipSuccess &&
-                        (!dw || hipMalloc((void **)&tw, sizeof(double) * std::max<i64>(c->g.m, 1)) == hipSuccess);
+    const bool zbuf = !on_device || c->seg, wbuf = !on_device && dw;
+    {
+        const bool ok = (!zbuf || hipMalloc((void **)&tZ, sizeof(double) * n) == hipSuccess) &&
+                        (!wbuf || hipMalloc((void **)&tw, sizeof(double) * std::max<i64>(c->g.m, 1)) == hipSuccess);
         if (!ok) {
             if (tZ) (void)hipFree(tZ);
             DI_FAIL(DI_ENOMEM, "device allocation for the gradients failed");
         }
-        ddZ = tZ;
-        ddw = dw ? tw : nullptr;
+        if (zbuf) ddZ = tZ;
+        if (wbuf) ddw = tw;
     }
     int rc = launch_edge_grad(c->g, c->s.H, c->lam, c->d, ddZ, ddw, c->st);
     DI_HIP(hipEventRecord(c->ev1, c->st));
-    if (rc == DI_OK && !on_device) {
-        if (hipMemcpyAsync(dZ, tZ, sizeof(double) * n, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
-            (dw && c->g.m && hipMemcpyAsync(dw, tw, sizeof(double) * c->g.m, hipMemcpyDeviceToHost, c->st) != hipSuccess))
-            rc = DI_EHIP;
+    std::vector<double> hz;
+    if (rc == DI_OK && zbuf) {
+        hz.resize((size_t)n);
+        if (hipMemcpyAsync(hz.data(), tZ, sizeof(double) * n, hipMemcpyDeviceToHost, c->st) != hipSuccess) rc = DI_EHIP;
     }
+    if (rc == DI_OK && wbuf && c->g.m &&
+        hipMemcpyAsync(dw, tw, sizeof(double) * c->g.m, hipMemcpyDeviceToHost, c->st) != hipSuccess)
+        rc = DI_EHIP;
     if (hipStreamSynchronize(c->st) != hipSuccess) rc = DI_EHIP;
     if (tZ) (void)hipFree(tZ);
     if (tw) (void)hipFree(tw);
     if (rc != DI_OK) DI_FAIL(rc, "adjoint gradient step failed");
+    if (zbuf) {  // dZ in the caller's numbering
+        std::vector<double> zc;
+        const double *zout = hz.data();
+        if (c->seg) {
+            zc.resize((size_t)nu);
+            seg_compact(c, hz.data(), zc.data());
+            zout = zc.data();
+        }
+        if (on_device) DI_HIP(hipMemcpy(dZ, zout, sizeof(double) * nu, hipMemcpyHostToDevice));
+        else std::memcpy(dZ, zout, sizeof(double) * nu);
+    }
     DI_TRY(sync_ctl(c, c->actl));
     float ms = 0.0f;
     DI_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));

@@ -45,16 +45,24 @@ def oracle_graphs():
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("name", list(GRAPHS))
 @pytest.mark.parametrize("rb", [8, 13])
-def test_in_adjacency_bit_exact(gpu, oracle_graphs, name, rb):
+@pytest.mark.parametrize("cut", [-1, 0])
+def test_in_adjacency_bit_exact(gpu, oracle_graphs, name, rb, cut):
+    """IN, 1/s and the local/cross-range split; with cut-aligned ranges (cut = 0) IN and 1/s
+    are read back through the relabelling and must still equal the oracle's."""
     g, og = GRAPHS[name], oracle_graphs[name]
-    say("graph build", name, "rb", rb)
-    with gpu.from_graph(g, range_log2=rb) as s:
+    say("graph build", name, "rb", rb, "cut", cut)
+    with gpu.from_graph(g, range_log2=rb, range_cut=cut) as s:
         np.testing.assert_array_equal(s.read(gpu.IN_PTR), og.in_ptr)
         np.testing.assert_array_equal(s.read(gpu.IN_IDX), og.in_idx)
         np.testing.assert_array_equal(s.read(gpu.INV_S), og.inv_s)
-        m_loc = s.info(gpu.INFO_M_LOCAL)
-        src = np.repeat(np.arange(g.n), np.diff(g.out_ptr))
-        assert m_loc == int(((src >> rb) == (g.out_idx.astype(np.int64) >> rb)).sum())
+        m_loc, m_rem = s.info(gpu.INFO_M_LOCAL), s.info(gpu.INFO_M_REMOTE)
+        assert m_loc + m_rem == g.m
+        assert s.info(gpu.INFO_N) == g.n
+        if cut == -1:
+            src = np.repeat(np.arange(g.n), np.diff(g.out_ptr))
+            assert m_loc == int(((src >> rb) == (g.out_idx.astype(np.int64) >> rb)).sum())
+        else:  # ranges end at the caller's cut points: no range exceeds 2^rb caller nodes
+            assert g.n <= s.info(gpu.INFO_N_INTERNAL) <= 2 * g.n + (1 << rb)
 
 
 # --------------------------------------------------------------------------
