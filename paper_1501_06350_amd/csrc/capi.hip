@@ -546,7 +546,7 @@ int di_destroy(di_ctx *c) {
     free_row_blocks(c->rbout);
     void *ps[] = {c->s.F, c->s.F0, c->s.H, c->s.S[0], c->s.S[1], c->s.snap, c->s.frontier, c->s.range_order,
                   c->s.ctl, c->s.X[0], c->s.X[1], c->s.XT[0], c->s.XT[1], c->s.pctl, c->s.Z, c->lam,
-                  c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.ginfo, c->s.gctl,
+                  c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.range_cnt, c->s.ginfo, c->s.gctl,
                   c->d_gp, c->d_gs, c->d_gscale, c->ref_ht};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -795,6 +795,18 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         if ((rc = dalloc(c, &c->s.range_order, nr))) return fail(rc);
         if (hipMemcpy(c->s.range_order, order.data(), sizeof(int) * nr, hipMemcpyHostToDevice) != hipSuccess) {
             set_error("range order upload failed");
+            return fail(DI_EHIP);
+        }
+    }
+
+    // cut-aligned ranges: the block-local sweeps skip the padding at the end of each range
+    if (c->seg) {
+        const i64 nr = c->g.nranges;
+        std::vector<int> cntv((size_t)nr);
+        for (i64 r = 0; r < nr; ++r) cntv[r] = (int)(c->seg_start[r + 1] - c->seg_start[r]);
+        if ((rc = dalloc(c, &c->s.range_cnt, nr))) return fail(rc);
+        if (hipMemcpy(c->s.range_cnt, cntv.data(), sizeof(int) * nr, hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("range table upload failed");
             return fail(DI_EHIP);
         }
     }

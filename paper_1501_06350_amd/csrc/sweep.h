@@ -75,6 +75,7 @@ struct SolveState {
     i64 nR = 0, nC = 0;
     // union of graphs (nullptr for one graph)
     int *range_graph = nullptr;  // nranges: graph of each range
+    int *range_cnt = nullptr;    // nranges: real nodes of each cut-aligned range (padding after them)
     GraphInfo *ginfo = nullptr;  // n_graphs
     GraphCtl *gctl = nullptr;    // n_graphs
     i64 n_graphs = 0;

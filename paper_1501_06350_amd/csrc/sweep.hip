@@ -74,6 +74,7 @@ struct BldArgs {
     int force;  // run even when the solve is marked done (delivery of fluid in flight)
     u64 *partR, *partC;  // per-workgroup partial sums (one slot per range)
     const int *range_graph;  // union of graphs: graph of each range (else nullptr)
+    const int *range_cnt;    // cut-aligned ranges: real nodes of each range (else nullptr)
     const GraphCtl *gctl;
 };
 
@@ -118,7 +119,8 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
     const int r = a.range_order[blockIdx.x];
     if (!range_schedule(a.range_graph, a.gctl, r, thr, rounds)) return;
     const i64 base = (i64)r << a.rb;
-    const int cnt = (int)min((i64)B, a.n - base);
+    // real nodes of the range (cut-aligned ranges end early; the rest is padding)
+    const int cnt = a.range_cnt ? a.range_cnt[r] : (int)min((i64)B, a.n - base);
     if (threadIdx.x == 0) bad = 0;
 
     // 1. fluid of the range, plus fluid sent here by other ranges last sweep
@@ -285,6 +287,7 @@ static BldArgs make_bld_args(const DevGraph &g, SolveState &s, const SweepParams
     a.partR = s.partR;
     a.partC = s.partC;
     a.range_graph = s.range_graph;
+    a.range_cnt = s.range_cnt;
     a.gctl = s.gctl;
     return a;
 }
@@ -321,6 +324,7 @@ struct Bld2Args {
     int rounds;
     int force;
     u64 *partR, *partC;
+    const int *range_cnt;
     const int *range_graph;
     const GraphCtl *gctl;
 };
@@ -368,7 +372,8 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     const int r = a.range_order[blockIdx.x];
     if (!range_schedule(a.range_graph, a.gctl, r, thr, rounds)) return;
     const i64 base = (i64)r << a.rb;
-    const int cnt = (int)min((i64)B, a.n - base);
+    // real nodes of the range (cut-aligned ranges end early; the rest is padding)
+    const int cnt = a.range_cnt ? a.range_cnt[r] : (int)min((i64)B, a.n - base);
     const i64 lb = a.loc_base[r];
     const int nloc = (int)(a.loc_base[r + 1] - lb);
     const int ncap = min(nloc, a.tcap);
@@ -646,6 +651,7 @@ int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int
         b.partR = s.partR;
         b.partC = s.partC;
         b.range_graph = s.range_graph;
+        b.range_cnt = s.range_cnt;
         b.gctl = s.gctl;
         s.nR = s.nC = g.nranges;
         if (p.fp32) k_bld2_sweep<float><<<(unsigned)g.nranges, thr, lds2, st>>>(b);
