@@ -413,9 +413,10 @@ def bench_adjoint():
     import numpy as np
     import workloads as W
     from paper_1501_06350_amd import binding as B
+    import torch
     g = W.webgen(2_000_000, 5, weighted=True)
-    c = W.normal_vector(g.n, 5)
-    out = {"workload": "webgen n=%d m=%d seed=5, LogNormal(0,1) weights, c ~ N(0,1), f64" % (g.n, g.m)}
+    c = torch.from_numpy(W.normal_vector(g.n, 5)).cuda()  # resident in HBM; dZ and dw stay there too
+    out = {"workload": "webgen n=%d m=%d seed=5, LogNormal(0,1) weights, c ~ N(0,1), f64, device arrays" % (g.n, g.m)}
     with B.from_graph(g, d=D) as s:
         s.diffuse(1e-11)
         s.adjoint(c, 1e-11)  # warm-up

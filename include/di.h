@@ -102,8 +102,9 @@ typedef struct {
  *                    slots become padding nodes without edges or fluid.  The internal
  *                    numbering keeps the caller's order (edges, rows and results are
  *                    mapped back), so every call behaves as on the caller's graph.
- *                    0 = auto (2^range_log2 / 2), -1 = ranges at multiples of
- *                    2^range_log2 (no padding) [0]
+ *                    Values above 2^range_log2 / 2 act as 2^range_log2 / 2.
+ *                    0 = auto (1024), -1 = ranges at multiples of 2^range_log2 (no
+ *                    padding) [0]
  *   stream         : hipStream_t to run on; NULL = the null stream
  */
 typedef struct {

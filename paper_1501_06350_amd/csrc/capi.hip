@@ -60,6 +60,7 @@ struct di_ctx {
     bool seg = false;
     int seg_rb = 0;
     std::vector<i64> seg_start;
+    i64 *d_seg_start = nullptr;  // device copy of seg_start
     int rounds = 8;
     int spc = 8;  // sweeps per host check
     double zsum = 1.0;  // sum of Z (single right-hand side)
@@ -492,13 +493,14 @@ int upload_segmented(di_ctx *c, const i64 *ptr, const int *idx, const float *w, 
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-    (void)hipFree(d_start);
     (void)hipFree(d_coarse);
     cleanup();
     if (!hip_ok(e)) {
         (void)hipFree(pptr);
+        (void)hipFree(d_start);
         return DI_EHIP;
     }
+    c->d_seg_start = d_start;
     c->g.out_ptr = pptr;
     c->g.n = n_int;
     c->seg = true;
@@ -506,6 +508,23 @@ int upload_segmented(di_ctx *c, const i64 *ptr, const int *idx, const float *w, 
     c->seg_start = std::move(start);
     (void)w;
     return DI_OK;
+}
+
+// the same two mappings on the device (grid-stride over internal nodes q)
+__global__ void k_seg_to_internal(const double *__restrict__ src, double *dst, const i64 *__restrict__ start, int rb,
+                                  i64 n_int) {
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < n_int; q += (i64)gridDim.x * blockDim.x) {
+        const i64 r = q >> rb, j = q & (((i64)1 << rb) - 1);
+        dst[q] = j < start[r + 1] - start[r] ? src[start[r] + j] : 0.0;
+    }
+}
+
+__global__ void k_seg_to_caller(const double *__restrict__ src, double *dst, const i64 *__restrict__ start, int rb,
+                                i64 n_int) {
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < n_int; q += (i64)gridDim.x * blockDim.x) {
+        const i64 r = q >> rb, j = q & (((i64)1 << rb) - 1);
+        if (j < start[r + 1] - start[r]) dst[start[r] + j] = src[q];
+    }
 }
 
 // caller array (n_user values) -> internal layout (padding gets fill)
@@ -546,7 +565,7 @@ int di_destroy(di_ctx *c) {
     free_row_blocks(c->rbout);
     void *ps[] = {c->s.F, c->s.F0, c->s.H, c->s.S[0], c->s.S[1], c->s.snap, c->s.frontier, c->s.range_order,
                   c->s.ctl, c->s.X[0], c->s.X[1], c->s.XT[0], c->s.XT[1], c->s.pctl, c->s.Z, c->lam,
-                  c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.range_cnt, c->s.ginfo, c->s.gctl,
+                  c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.range_cnt, c->d_seg_start, c->s.ginfo, c->s.gctl,
                   c->d_gp, c->d_gs, c->d_gscale, c->ref_ht};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -744,7 +763,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     const i64 B = (i64)1 << rb;
     std::vector<double> segz;
     if (k == 1 && opt.n_graphs == 1 && !opt.deterministic && opt.range_cut >= 0 && n > B) {
-        const i64 X = opt.range_cut == 0 ? B / 2 : std::min<i64>(opt.range_cut, B / 2);
+        const i64 X = std::min<i64>(opt.range_cut == 0 ? 1024 : opt.range_cut, B / 2);
         if ((rc = upload_segmented(c, ptr, idx, w, n, m, rb, X)) != DI_OK) return fail(rc);
         if (w && (rc = dalloc(c, &c->g.w, m))) return fail(rc);
         if (w && m && hipMemcpy(c->g.w, w, sizeof(float) * m, hipMemcpyHostToDevice) != hipSuccess) {
@@ -1374,7 +1393,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         DI_TRY(dalloc(c, &c->actl, 1));
     }
     const i64 nu = c->n_user;  // the caller's node count (n is internal)
-    std::vector<double> hg, gint;
+    std::vector<double> hg;
     const double *gsrc = g;
     double mx = 0.0;
     {
@@ -1387,16 +1406,21 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
             if (!std::isfinite(gsrc[i])) DI_FAIL(DI_EINVAL, "g[%lld] is not finite", (long long)i);
             mx = std::max(mx, std::fabs(gsrc[i]));
         }
-        if (c->seg) {  // internal layout: padding nodes get no g
-            gint.assign((size_t)n, 0.0);
-            seg_expand(c, gsrc, gint.data(), 0.0);
-            gsrc = gint.data();
-        }
     }
     SweepParams ap = c->p;
     ap.K = fixed_scale(mx, n);
     ap.tol = tol_inf;
-    DI_HIP(hipMemcpyAsync(c->aF, gsrc, sizeof(double) * n, hipMemcpyHostToDevice, c->st));
+    if (c->seg) {  // internal layout (padding nodes get no g), spread on the device
+        const double *gdev = g;
+        if (!on_device) {  // the snapshot buffer is free until the sweeps start
+            DI_HIP(hipMemcpyAsync(c->asnap, g, sizeof(double) * nu, hipMemcpyHostToDevice, c->st));
+            gdev = c->asnap;
+        }
+        k_seg_to_internal<<<grid_for(n, 256, 16384), 256, 0, c->st>>>(gdev, c->aF, c->d_seg_start, c->seg_rb, n);
+        DI_LAUNCH_CHECK();
+    } else {
+        DI_HIP(hipMemcpyAsync(c->aF, gsrc, sizeof(double) * n, hipMemcpyHostToDevice, c->st));
+    }
     DI_TRY(launch_fill_zero(c->lam, n * 8, c->st));
     DI_TRY(launch_fill_zero(c->actl, sizeof(DevCtl), c->st));
     DI_HIP(hipEventRecord(c->ev0, c->st));
@@ -1445,11 +1469,18 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         if (wbuf) ddw = tw;
     }
     int rc = launch_edge_grad(c->g, c->s.H, c->lam, c->d, ddZ, ddw, c->st);
+    if (rc == DI_OK && c->seg) {  // dZ back to the caller's numbering (device dZ, or the snapshot buffer)
+        double *zc = on_device ? dZ : c->asnap;
+        k_seg_to_caller<<<grid_for(n, 256, 16384), 256, 0, c->st>>>(tZ, zc, c->d_seg_start, c->seg_rb, n);
+        if (hipGetLastError() != hipSuccess) rc = DI_EHIP;
+    }
     DI_HIP(hipEventRecord(c->ev1, c->st));
     std::vector<double> hz;
-    if (rc == DI_OK && zbuf) {
-        hz.resize((size_t)n);
-        if (hipMemcpyAsync(hz.data(), tZ, sizeof(double) * n, hipMemcpyDeviceToHost, c->st) != hipSuccess) rc = DI_EHIP;
+    if (rc == DI_OK && !on_device) {
+        hz.resize((size_t)nu);
+        if (hipMemcpyAsync(hz.data(), c->seg ? c->asnap : tZ, sizeof(double) * nu, hipMemcpyDeviceToHost, c->st) !=
+            hipSuccess)
+            rc = DI_EHIP;
     }
     if (rc == DI_OK && wbuf && c->g.m &&
         hipMemcpyAsync(dw, tw, sizeof(double) * c->g.m, hipMemcpyDeviceToHost, c->st) != hipSuccess)
@@ -1458,17 +1489,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     if (tZ) (void)hipFree(tZ);
     if (tw) (void)hipFree(tw);
     if (rc != DI_OK) DI_FAIL(rc, "adjoint gradient step failed");
-    if (zbuf) {  // dZ in the caller's numbering
-        std::vector<double> zc;
-        const double *zout = hz.data();
-        if (c->seg) {
-            zc.resize((size_t)nu);
-            seg_compact(c, hz.data(), zc.data());
-            zout = zc.data();
-        }
-        if (on_device) DI_HIP(hipMemcpy(dZ, zout, sizeof(double) * nu, hipMemcpyHostToDevice));
-        else std::memcpy(dZ, zout, sizeof(double) * nu);
-    }
+    if (!on_device) std::memcpy(dZ, hz.data(), sizeof(double) * nu);
     DI_TRY(sync_ctl(c, c->actl));
     float ms = 0.0f;
     DI_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
