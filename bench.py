@@ -117,7 +117,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--range-log2", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=0)
-    ap.add_argument("--theta", type=float, default=1.0)
+    ap.add_argument("--theta", type=float, default=0.3,
+                    help="frontier scale of the sweeps (1.0 = the paper's at-least-average rule; also reported)")
     ap.add_argument("--range-cut", type=int, default=0, help="range_cut option (-1: ranges at multiples of 2^rb)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a copy of known size, then one DI solve")
@@ -199,6 +200,16 @@ def main():
                              kernel="k_bld2_sweep<%s>" % ("float" if fp32 else "double"),
                              launches=di["kern_launch"], avg_us=round(di["avg_ns"] / 1e3, 2)),
     }
+
+    # the paper's frontier rule (theta = 1: at least the average fluid), same precision
+    if args.theta != 1.0:
+        o1 = dict(opts, theta=1.0)
+        s1 = B.from_graph(g, d=D, fluid_fp32=fp32, **o1)
+        d1 = time_di(s1, args.steps, args.warmup, n, m)
+        s1.close()
+        result["di_theta_1"] = {"ms": round(d1["ms"], 3), "sweeps": d1["sweeps"], "edge_updates": d1["edges"],
+                                "geups": round(d1["geups"], 3), "bound": d1["bound"],
+                                "speedup_vs_pi": round(pi["ms"] / d1["ms"], 3)}
 
     # the other fluid precision (float fluid, double history: the precision extension), with
     # the float-x/s power iteration on the same context
@@ -292,7 +303,7 @@ def traffic_probe(args, fp32):
         y.copy_(x)
     torch.cuda.synchronize()
     g = W.webgen(args.n, args.seed)
-    with B.from_graph(g, d=D, fluid_fp32=fp32) as s:
+    with B.from_graph(g, d=D, fluid_fp32=fp32, theta=args.theta, range_cut=args.range_cut) as s:
         st = s.diffuse(TOL)
     torch.cuda.synchronize()
     log("traffic probe: copies of %d bytes, then %d sweeps, source sha256 %s" %
