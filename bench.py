@@ -196,7 +196,8 @@ def main():
         "pi": {"x_over_s": "f64", "iterations": pi["iterations"], "geups": round(pi["geups"], 3),
                "l1_diff_to_di": di_pi_l1, "roofline": roofline(pi["achieved"])},
         "di_pi_l1_diff": di_pi_l1,
-        "roofline": roofline(di["achieved"], traffic=measured_traffic("f32" if fp32 else "f64"),
+        "roofline": roofline(di["achieved"],
+                             traffic=measured_traffic("f32" if fp32 else "f64", args.theta, args.range_cut),
                              kernel="k_bld2_sweep<%s>" % ("float" if fp32 else "double"),
                              launches=di["kern_launch"], avg_us=round(di["avg_ns"] / 1e3, 2)),
     }
@@ -271,9 +272,14 @@ def sweep_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(prec):
+def traffic_options(theta, range_cut):
+    return "theta=%g range_cut=%d" % (theta, range_cut)
+
+
+def measured_traffic(prec, theta, range_cut):
     """HBM bytes per launch of the block-local sweep from the committed counter profile,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the sources or the sweep options differ from those the counters were
+    taken with."""
     try:
         text = open(traffic_profile(prec)).read()
     except OSError:
@@ -283,7 +289,7 @@ def measured_traffic(prec):
         if ":" in line and line.startswith("- "):
             key, val = line[2:].split(":", 1)
             vals[key.strip()] = val.strip().strip("`")
-    if vals.get("source sha256") != sweep_source_hash():
+    if vals.get("source sha256") != sweep_source_hash() or vals.get("options") != traffic_options(theta, range_cut):
         return None
     try:
         return float(vals["traffic bytes per launch"])
