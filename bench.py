@@ -327,9 +327,10 @@ def _timed(fn):
 
 def bench_batched(fp32):
     """Personalized PageRank, webgen(4M, seed 4), k=64 columns of 16 seeds each, L1 tol 1e-8
-    per column: one k=64 tile solve (float fluid, the tile's precision) vs 64 single-column
-    solves on the same resident graph (di_set_z between them, outside the timed calls), in
-    float and in double fluid; the speedup is taken against the faster of the two."""
+    per column: one k=64 tile solve (float fluid, the tile's precision, theta 1: its best) vs
+    64 single-column solves on the same resident graph (di_set_z between them, outside the
+    timed calls) in float and double fluid at theta 1 and 0.5; the speedup is taken against
+    the fastest of the four."""
     import numpy as np
     import workloads as W
     from paper_1501_06350_amd import binding as B
@@ -338,18 +339,22 @@ def bench_batched(fp32):
     out = {"workload": "webgen n=%d m=%d seed=4, k=64 x 16 seeds, f32 fluid tile" % (g.n, g.m)}
     singles = {}
     for prec in ("f32", "f64"):
-        total, sweeps = 0.0, 0
-        with B.from_graph(g, d=D, Z=np.ascontiguousarray(Z[:, 0]), fluid_fp32=prec == "f32") as sc:
-            sc.diffuse(TOL)  # warm-up
-            for c in range(64):
-                sc.set_z(np.ascontiguousarray(Z[:, c]))
-                st, ms = _timed(lambda: sc.diffuse(TOL))
-                total += ms
-                sweeps += st["sweeps"]
-        singles[prec] = (total, sweeps / 64)
-        out["single_%s_total_ms" % prec] = round(total, 3)
-        out["single_%s_mean_sweeps" % prec] = round(sweeps / 64, 2)
-    best = min(v[0] for v in singles.values())
+        for th in (1.0, 0.5):
+            total, sweeps = 0.0, 0
+            with B.from_graph(g, d=D, Z=np.ascontiguousarray(Z[:, 0]), fluid_fp32=prec == "f32", theta=th) as sc:
+                sc.diffuse(TOL)  # warm-up
+                for c in range(64):
+                    sc.set_z(np.ascontiguousarray(Z[:, c]))
+                    st, ms = _timed(lambda: sc.diffuse(TOL))
+                    total += ms
+                    sweeps += st["sweeps"]
+            key = "%s_theta%g" % (prec, th)
+            singles[key] = (total, sweeps / 64)
+            out["single_%s_total_ms" % key] = round(total, 3)
+            out["single_%s_mean_sweeps" % key] = round(sweeps / 64, 2)
+    best_key = min(singles, key=lambda q: singles[q][0])
+    best = singles[best_key][0]
+    out["best_single"] = best_key
     with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=fp32) as sb:
         sb.diffuse(TOL)  # warm-up
         sb.reset()
@@ -357,7 +362,7 @@ def bench_batched(fp32):
         assert st["converged"]
     out["batched_ms"] = round(ms, 3)
     out["speedup"] = round(best / ms, 3)
-    out["speedup_same_precision"] = round(singles["f32" if fp32 else "f64"][0] / ms, 3)
+    out["speedup_same_precision"] = round(singles["%s_theta1" % ("f32" if fp32 else "f64")][0] / ms, 3)
     out["batched_sweeps"] = st["sweeps"]
     out["edge_column_updates"] = st["edge_updates"]
     out["geups_edge_columns"] = round(st["edge_updates"] / (ms * 1e-3) / 1e9, 3)
