@@ -330,13 +330,77 @@ struct Bld2Args {
 };
 
 // LDS layout of k_bld2_sweep (bytes): F[B], dH[B] (fluid type), deg[B], off[B+1] (u32),
-// padding to 8, then per wave 64 x (q double, start u32, offset i32), then the targets.
+// padding to 8, then per wave 64 x (q double, start u32, offset i32), per wave a bitmap of
+// BLD2_SLOTS bits, then the targets.
 __host__ __device__ inline size_t bld2_scratch_offset(int B, int tsize) {
     return ((size_t)2 * B * tsize + (size_t)4 * (2 * B + 1) + 7) & ~(size_t)7;
 }
 
+// edge slots one wave lists before it pushes them (a multiple of 4 x 64)
+constexpr int BLD2_SLOTS = 1024;
+
 size_t bld2_fixed_lds(int rb, int fp32, int threads) {
-    return bld2_scratch_offset(1 << rb, fp32 ? 4 : 8) + (size_t)(threads / WAVE) * WAVE * (8 + 4 + 4);
+    return bld2_scratch_offset(1 << rb, fp32 ? 4 : 8) +
+           (size_t)(threads / WAVE) * (WAVE * (8 + 4 + 4) + BLD2_SLOTS / 8);
+}
+
+// Pushes the local edges of the nodes a wave has listed: listed node k sends sc_q[k] along
+// its edges, which occupy the slots [o_k, o_{k+1}) of [0, ltot); bit o_k of the wave's
+// bitmap is set and sc_base[k] = (start of k's targets) - o_k.  A lane finds the node of
+// its slot s from the 64-bit bitmap word holding s (the same word for the whole wave) and
+// the running count of set bits before it; no search.  Slots past ltot push nothing.  The
+// bitmap is cleared on return.
+template <typename T>
+__device__ __forceinline__ void bld2_push_list(T *Fl, const unsigned short *Tg, int tdelta, int ncap,
+                                               const unsigned short *loc_tgt, i64 lb,
+                                               const int *sc_base, const double *sc_q,
+                                               unsigned *sc_bits, int ltot, int lane) {
+    wave_sync_lds();
+    constexpr int EDGE_U = 4;
+    int pre = 0;  // listed nodes that start before the current window
+    for (int sb = 0; sb < ltot; sb += WAVE * EDGE_U) {
+        unsigned tgt[EDGE_U];
+        double val[EDGE_U];
+        unsigned pp[EDGE_U];
+#pragma unroll
+        for (int u = 0; u < EDGE_U; ++u) {
+            const int wd = (sb >> 5) + 2 * u;  // 32-bit words of the window [sb + 64u, +64)
+            const unsigned lo = __builtin_amdgcn_readfirstlane(sc_bits[wd]);
+            const unsigned hi = __builtin_amdgcn_readfirstlane(sc_bits[wd + 1]);
+            const unsigned below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            const unsigned mine = ((lane < 32 ? lo >> lane : hi >> (lane - 32)) & 1u);
+            const int k = pre + (int)(below + mine) - 1;
+            pre += __builtin_popcount(lo) + __builtin_popcount(hi);
+            const int sl = sb + u * WAVE + lane;
+            pp[u] = sl < ltot ? (unsigned)(sc_base[k] + sl) : 0u;
+            val[u] = sc_q[k];
+        }
+        bool staged = true;
+#pragma unroll
+        for (int u = 0; u < EDGE_U; ++u) staged = staged && (int)pp[u] < ncap;
+        if (__ballot(!staged) == 0) {
+#pragma unroll
+            for (int u = 0; u < EDGE_U; ++u) tgt[u] = Tg[tdelta + pp[u]];
+        } else {
+#pragma unroll
+            for (int u = 0; u < EDGE_U; ++u) {
+                unsigned t;
+                if ((int)pp[u] < ncap) {
+                    t = Tg[tdelta + pp[u]];
+                } else {
+                    t = loc_tgt[lb + pp[u]];
+                    asm volatile("" : "+v"(t));
+                }
+                tgt[u] = t;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < EDGE_U; ++u)
+            if (sb + u * WAVE + lane < ltot) atomicAdd(&Fl[tgt[u]], (T)val[u]);
+    }
+    wave_sync_lds();
+    for (int wd = lane; wd < ((ltot + 255) >> 8) * 8; wd += WAVE) sc_bits[wd] = 0u;
+    wave_sync_lds();
 }
 
 template <typename T>
@@ -354,10 +418,12 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     double *sc_q_all = reinterpret_cast<double *>(smem + bld2_scratch_offset(B, (int)sizeof(T)));
     unsigned *sc_start_all = reinterpret_cast<unsigned *>(sc_q_all + nw * WAVE);
     int *sc_off_all = reinterpret_cast<int *>(sc_start_all + nw * WAVE);
-    unsigned short *Tg = reinterpret_cast<unsigned short *>(sc_off_all + nw * WAVE);
+    unsigned *sc_bits_all = reinterpret_cast<unsigned *>(sc_off_all + nw * WAVE);
+    unsigned short *Tg = reinterpret_cast<unsigned short *>(sc_bits_all + nw * (BLD2_SLOTS / 32));
     double *sc_q = sc_q_all + w * WAVE;
     unsigned *sc_start = sc_start_all + w * WAVE;
     int *sc_off = sc_off_all + w * WAVE;
+    unsigned *sc_bits = sc_bits_all + w * (BLD2_SLOTS / 32);
     __shared__ u64 red[PSC * 16];
     __shared__ int bad;
 
@@ -378,6 +444,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     const int nloc = (int)(a.loc_base[r + 1] - lb);
     const int ncap = min(nloc, a.tcap);
     if (threadIdx.x == 0) bad = 0;
+    for (int wd = threadIdx.x; wd < nw * (BLD2_SLOTS / 32); wd += nthr) sc_bits_all[wd] = 0u;
 
     // 1. stage the range; every loop keeps SU independent loads in flight per thread
     // (out-of-range slots load a valid clamped address and store nothing)
@@ -467,6 +534,9 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     u64 nodes = 0, edges = 0;
     for (int round = 0; round < rounds; ++round) {
         bool any = false;
+        // nodes taken in this round are listed across the wave's chunks and their edges
+        // pushed together once the list is full: ln nodes, ltot edge slots (wave-uniform)
+        int ln = 0, ltot = 0;
         for (int c = my0; c < my1; c += WAVE) {
             const int i = c + lane;
             double f = 0.0;
@@ -491,62 +561,66 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                 }
                 ++nodes;
             }
-            // the nodes with edges to push, listed in lane order: their edge lists are
-            // consecutive in the slot space [0, total)
+            // the nodes with edges to push, in lane order: their edge lists are consecutive
+            // in the slot space [0, total) of this chunk
             const u64 pm = __ballot(dg > 0);
             const int nact = __popcll(pm);
             const int inc = wave_incl_scan_i32(dg);
             const int total = __shfl(inc, WAVE - 1, WAVE);
+            edges += (lane == 0) ? (u64)total : 0ull;
+            if (total == 0) continue;
+            const int rk = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(pm >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)pm, 0u));
+            if (ln + nact > WAVE || ltot + total > BLD2_SLOTS) {
+                bld2_push_list<T>(Fl, Tg, tdelta, ncap, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start),
+                                  sc_q, sc_bits, ltot, lane);
+                ln = 0;
+                ltot = 0;
+            }
+            if (total <= BLD2_SLOTS) {
+                if (dg > 0) {
+                    const int pos = ltot + inc - dg;
+                    sc_start[ln + rk] = (unsigned)((int)st - pos);
+                    sc_q[ln + rk] = q;
+                    atomicOr(&sc_bits[pos >> 5], 1u << (pos & 31));
+                }
+                ln += nact;
+                ltot += total;
+                continue;
+            }
+            // a chunk with more edge slots than a list holds: its own pass, the slot's node
+            // found by binary search over the chunk's nact nodes
             if (dg > 0) {
-                const int rk = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(pm >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((unsigned)pm, 0u));
                 sc_start[rk] = st;
                 sc_off[rk] = inc - dg;
                 sc_q[rk] = q;
             }
             wave_sync_lds();
-            edges += (lane == 0) ? (u64)total : 0ull;
-            // binary search depth over the nact listed nodes (uniform across the wave)
             const int depth = nact > 1 ? 32 - __builtin_clz((unsigned)(nact - 1)) : 0;
             constexpr int EDGE_U = 4;
             for (int sb = lane; sb < total; sb += WAVE * EDGE_U) {
                 unsigned tgt[EDGE_U];
                 double val[EDGE_U];
-                unsigned pp[EDGE_U];
 #pragma unroll
                 for (int u = 0; u < EDGE_U; ++u) {
-                    const int s = min(sb + u * WAVE, total - 1);
-                    int lo = 0, hi = nact - 1;  // last listed node k with sc_off[k] <= s
+                    const int sl = min(sb + u * WAVE, total - 1);
+                    int lo = 0, hi = nact - 1;  // last listed node k with sc_off[k] <= sl
                     for (int it = 0; it < depth; ++it) {
                         const int mid = (lo + hi + 1) >> 1;
-                        const bool le = sc_off[mid] <= s;
+                        const bool le = sc_off[mid] <= sl;
                         lo = le ? mid : lo;
                         hi = le ? hi : mid - 1;
                     }
-                    pp[u] = sc_start[lo] + (unsigned)(s - sc_off[lo]);
-                    val[u] = sc_q[lo];
-                }
-                // targets from the staged LDS copy when every slot of the batch lies in it
-                // (the usual case), else per slot from LDS or global memory (the empty asm
-                // keeps the two loads apart, so the LDS one stays an LDS access)
-                bool staged = true;
-#pragma unroll
-                for (int u = 0; u < EDGE_U; ++u) staged = staged && (int)pp[u] < ncap;
-                if (__ballot(!staged) == 0) {
-#pragma unroll
-                    for (int u = 0; u < EDGE_U; ++u) tgt[u] = Tg[tdelta + pp[u]];
-                } else {
-#pragma unroll
-                    for (int u = 0; u < EDGE_U; ++u) {
-                        unsigned t;
-                        if ((int)pp[u] < ncap) {
-                            t = Tg[tdelta + pp[u]];
-                        } else {
-                            t = a.loc_tgt[lb + pp[u]];
-                            asm volatile("" : "+v"(t));
-                        }
-                        tgt[u] = t;
+                    const unsigned pp = sc_start[lo] + (unsigned)(sl - sc_off[lo]);
+                    unsigned t;
+                    if ((int)pp < ncap) {
+                        t = Tg[tdelta + pp];
+                    } else {
+                        t = a.loc_tgt[lb + pp];
+                        asm volatile("" : "+v"(t));
                     }
+                    tgt[u] = t;
+                    val[u] = sc_q[lo];
                 }
 #pragma unroll
                 for (int u = 0; u < EDGE_U; ++u)
@@ -554,6 +628,9 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             }
             wave_sync_lds();
         }
+        if (ltot > 0)
+            bld2_push_list<T>(Fl, Tg, tdelta, ncap, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start), sc_q,
+                              sc_bits, ltot, lane);
         if (!any) break;
     }
     __syncthreads();
