@@ -37,6 +37,18 @@ __device__ __forceinline__ T lds_load(T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// inclusive prefix sum over the 64 lanes of a wave with DPP moves (rows of 16 by shifts of
+// 1, 2, 4 and 8, then lane 15 of each row into the next row, then lane 31 into rows 2 and 3)
+__device__ __forceinline__ int wave_incl_scan_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -351,7 +363,7 @@ size_t bld2_fixed_lds(int rb, int fp32, int threads) {
 // the running count of set bits before it; no search.  Slots past ltot push nothing.  The
 // bitmap is cleared on return.
 template <typename T>
-__device__ __forceinline__ void bld2_push_list(T *Fl, const unsigned short *Tg, int tdelta, int ncap,
+__device__ __forceinline__ void bld2_push_list(T *Fl, const unsigned short *Tg, int tdelta, int ncap, int nloc,
                                                const unsigned short *loc_tgt, i64 lb,
                                                const int *sc_base, const double *sc_q,
                                                unsigned *sc_bits, int ltot, int lane) {
@@ -388,7 +400,7 @@ __device__ __forceinline__ void bld2_push_list(T *Fl, const unsigned short *Tg, 
                 if ((int)pp[u] < ncap) {
                     t = Tg[tdelta + pp[u]];
                 } else {
-                    t = loc_tgt[lb + pp[u]];
+                    t = loc_tgt[lb + min((int)pp[u], nloc - 1)];
                     asm volatile("" : "+v"(t));
                 }
                 tgt[u] = t;
@@ -539,10 +551,19 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
         int ln = 0, ltot = 0;
         for (int c = my0; c < my1; c += WAVE) {
             const int i = c + lane;
+            const bool own = i < my1;
+            const int ii = own ? i : my0;  // lanes past the share load the first node
+            // the node's degree, offsets and 1/degree load and compute while its fluid
+            // value is read; a taken node gives up exactly the value read (a subtraction
+            // without return), so fluid that reached it in the meantime stays
+            const T v = lds_load(&Fl[ii]);
+            const unsigned deg = Deg[ii] & 0x7fffffffu;
+            const unsigned o0 = Off[ii], o1 = Off[ii + 1];
+            const double rdeg = 1.0 / (double)(deg ? deg : 1u);
             double f = 0.0;
-            if (i < my1) {
-                T v = lds_load(&Fl[i]);
-                if (v != (T)0 && fabs((double)v) >= thr) f = (double)atomicExch(&Fl[i], (T)0);
+            if (own && v != (T)0 && fabs((double)v) >= thr) {
+                f = (double)v;
+                atomicAdd(&Fl[i], -v);
             }
             if (__ballot(f != 0.0) == 0) continue;
             any = true;
@@ -551,13 +572,12 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             double q = 0.0;
             if (f != 0.0) {
                 Dl[i] = (T)((double)Dl[i] + f);
-                const unsigned deg = Deg[i] & 0x7fffffffu;
                 if (deg == 0) {
                     Ld += fabs(f);
                 } else {
-                    q = (a.d * f) * (1.0 / (double)deg);
-                    st = Off[i];
-                    dg = (int)(Off[i + 1] - st);
+                    q = (a.d * f) * rdeg;
+                    st = o0;
+                    dg = (int)(o1 - o0);
                 }
                 ++nodes;
             }
@@ -565,14 +585,14 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             // in the slot space [0, total) of this chunk
             const u64 pm = __ballot(dg > 0);
             const int nact = __popcll(pm);
-            const int inc = wave_incl_scan_i32(dg);
-            const int total = __shfl(inc, WAVE - 1, WAVE);
+            const int inc = wave_incl_scan_dpp(dg);
+            const int total = __builtin_amdgcn_readlane(inc, WAVE - 1);
             edges += (lane == 0) ? (u64)total : 0ull;
             if (total == 0) continue;
             const int rk = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(pm >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((unsigned)pm, 0u));
             if (ln + nact > WAVE || ltot + total > BLD2_SLOTS) {
-                bld2_push_list<T>(Fl, Tg, tdelta, ncap, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start),
+                bld2_push_list<T>(Fl, Tg, tdelta, ncap, nloc, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start),
                                   sc_q, sc_bits, ltot, lane);
                 ln = 0;
                 ltot = 0;
@@ -616,7 +636,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                     if ((int)pp < ncap) {
                         t = Tg[tdelta + pp];
                     } else {
-                        t = a.loc_tgt[lb + pp];
+                        t = a.loc_tgt[lb + min((int)pp, nloc - 1)];
                         asm volatile("" : "+v"(t));
                     }
                     tgt[u] = t;
@@ -629,7 +649,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             wave_sync_lds();
         }
         if (ltot > 0)
-            bld2_push_list<T>(Fl, Tg, tdelta, ncap, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start), sc_q,
+            bld2_push_list<T>(Fl, Tg, tdelta, ncap, nloc, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start), sc_q,
                               sc_bits, ltot, lane);
         if (!any) break;
     }
