@@ -116,7 +116,8 @@ def main():
     ap.add_argument("--no-f32-leg", action="store_true", help="skip the float-fluid D-Iteration leg")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--range-log2", type=int, default=0)
-    ap.add_argument("--rounds", type=int, default=0)
+    ap.add_argument("--rounds", type=int, default=6,
+                    help="block-local rounds per sweep on the 50M graph (0: the library's default, 4)")
     ap.add_argument("--theta", type=float, default=0.3,
                     help="frontier scale of the sweeps (1.0 = the paper's at-least-average rule; also reported)")
     ap.add_argument("--range-cut", type=int, default=0, help="range_cut option (-1: ranges at multiples of 2^rb)")
@@ -197,7 +198,7 @@ def main():
                "l1_diff_to_di": di_pi_l1, "roofline": roofline(pi["achieved"])},
         "di_pi_l1_diff": di_pi_l1,
         "roofline": roofline(di["achieved"],
-                             traffic=measured_traffic("f32" if fp32 else "f64", args.theta, args.range_cut),
+                             traffic=measured_traffic("f32" if fp32 else "f64", args.theta, args.range_cut, used_rounds),
                              kernel="k_bld2_sweep<%s>" % ("float" if fp32 else "double"),
                              launches=di["kern_launch"], avg_us=round(di["avg_ns"] / 1e3, 2)),
     }
@@ -272,11 +273,11 @@ def sweep_source_hash():
     return h.hexdigest()
 
 
-def traffic_options(theta, range_cut):
-    return "theta=%g range_cut=%d" % (theta, range_cut)
+def traffic_options(theta, range_cut, rounds):
+    return "theta=%g range_cut=%d rounds=%d" % (theta, range_cut, rounds)
 
 
-def measured_traffic(prec, theta, range_cut):
+def measured_traffic(prec, theta, range_cut, rounds):
     """HBM bytes per launch of the block-local sweep from the committed counter profile,
     or None when the sources or the sweep options differ from those the counters were
     taken with."""
@@ -289,7 +290,7 @@ def measured_traffic(prec, theta, range_cut):
         if ":" in line and line.startswith("- "):
             key, val = line[2:].split(":", 1)
             vals[key.strip()] = val.strip().strip("`")
-    if vals.get("source sha256") != sweep_source_hash() or vals.get("options") != traffic_options(theta, range_cut):
+    if vals.get("source sha256") != sweep_source_hash() or vals.get("options") != traffic_options(theta, range_cut, rounds):
         return None
     try:
         return float(vals["traffic bytes per launch"])
@@ -309,11 +310,13 @@ def traffic_probe(args, fp32):
         y.copy_(x)
     torch.cuda.synchronize()
     g = W.webgen(args.n, args.seed)
-    with B.from_graph(g, d=D, fluid_fp32=fp32, theta=args.theta, range_cut=args.range_cut) as s:
+    with B.from_graph(g, d=D, fluid_fp32=fp32, theta=args.theta, range_cut=args.range_cut,
+                      inner_rounds=args.rounds) as s:
         st = s.diffuse(TOL)
+        rounds = s.info(B.INFO_INNER_ROUNDS)
     torch.cuda.synchronize()
-    log("traffic probe: copies of %d bytes, then %d sweeps, source sha256 %s" %
-        (COPY_BYTES, st["sweeps"], sweep_source_hash()))
+    log("traffic probe: copies of %d bytes, then %d sweeps, source sha256 %s, options %s" %
+        (COPY_BYTES, st["sweeps"], sweep_source_hash(), traffic_options(args.theta, args.range_cut, rounds)))
 
 
 def _timed(fn):
