@@ -203,6 +203,10 @@ constexpr double REFINE_DROP = 0x1p-14;
 // while the fluid is float, sweeps aim at REFINE_MARGIN * tol so that the residual of
 // the recomputed fluid (the float pushes' rounding added back) still meets tol
 constexpr double REFINE_MARGIN = 0.5;
+// share of the cross-range entries that must carry fluid in a block-local sweep for the
+// next one to read the in-flight values without testing the bitmap (on the 50M web graph
+// the direct reads win at about 0.6 of the entries live, the bitmap at about 0.4)
+constexpr double DENSE_DELIVERY = 0.5;
 
 int refine_fluid(di_ctx *c, double tol) {
     const size_t T = c->p.fp32 ? 4 : 8;
@@ -793,6 +797,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     c->p.rounds = c->rounds;
     c->spc = opt.sweeps_per_sync ? opt.sweeps_per_sync : 8;
     if ((rc = build_graph(c->g, c->g.out_ptr, c->g.out_idx, c->g.w, rb, k == 1, c->st)) != DI_OK) return fail(rc);
+    c->p.dense_at = DENSE_DELIVERY * (double)c->g.m_rem;
     c->device_bytes += (2 * (n + 1) + 3 * n) * 8 + m * (4 + (w ? 4 : 0)) + c->g.m_loc * (2 + (w ? 4 : 0)) +
                        c->g.m_rem * (6 + (w ? 4 : 0)) + (c->g.nranges + 1) * 16;
 

@@ -215,6 +215,7 @@ struct DevCtl {
     int parity;         // slot written by the next sweep
     long long sweep;    // sweeps run since reset
     long long budget;   // sweep limit of the running call (absolute sweep index)
+    int dense;          // the next block-local sweep reads in-flight values without the bitmap
 };
 
 

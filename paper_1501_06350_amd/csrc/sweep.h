@@ -98,6 +98,9 @@ struct SweepParams {
     i64 n = 0;
     double zsum = 1.0;  // normalised stop uses l / zsum
     int bld_v1 = 0;     // force the global-memory block-local kernel
+    // the block-local sweep after one that delivered at least this many nonzero in-flight
+    // values reads them without testing the bitmap first (0: always test)
+    double dense_at = 0.0;
 };
 
 // Kernels launched by the solver driver (all on stream st).

@@ -506,10 +506,12 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     }
     __syncthreads();
 
-    // 2. fluid sent here by other ranges last sweep; a source's value is gathered only
-    // when its bit in the in-flight bitmap is set (most sources send nothing in a sweep,
-    // and a random 4-byte gather costs a full line)
+    // 2. fluid sent here by other ranges last sweep.  Every source with cross-range
+    // edges wrote its value (zero included) and its bit in the in-flight bitmap; when few
+    // sources sent, a value is gathered only if its bit is set (a random read costs a
+    // full line), else every value is read directly
     u64 delivered = 0;
+    const bool dense = ctl->dense != 0;
     {
         constexpr int REM_U = 8;
         const i64 p0 = a.rem_base[r], p1 = a.rem_base[r + 1];
@@ -522,12 +524,17 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                 src[u] = a.rem_src[p];
                 tg[u] = (unsigned)a.rem_tgt[p];
             }
-            u64 wd[REM_U];
-#pragma unroll
-            for (int u = 0; u < REM_U; ++u) wd[u] = Sbprev[src[u] >> 6];
             T v[REM_U];
+            if (dense) {
 #pragma unroll
-            for (int u = 0; u < REM_U; ++u) v[u] = ((wd[u] >> (src[u] & 63)) & 1ull) ? Sprev[src[u]] : (T)0;
+                for (int u = 0; u < REM_U; ++u) v[u] = Sprev[src[u]];
+            } else {
+                u64 wd[REM_U];
+#pragma unroll
+                for (int u = 0; u < REM_U; ++u) wd[u] = Sbprev[src[u] >> 6];
+#pragma unroll
+                for (int u = 0; u < REM_U; ++u) v[u] = ((wd[u] >> (src[u] & 63)) & 1ull) ? Sprev[src[u]] : (T)0;
+            }
 #pragma unroll
             for (int u = 0; u < REM_U; ++u) {
                 if (pb + (i64)u * nthr < p1 && v[u] != (T)0) {
@@ -666,11 +673,13 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     for (int i0 = threadIdx.x; i0 < cnt; i0 += nthr * SU) {
         double hv[SU], rwv[SU], dh[SU];
         T sv[SU];
+        bool rm[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int i = min(i0 + u * nthr, cnt - 1);
             dh[u] = (double)Dl[i];
             const unsigned df = Deg[i];
+            rm[u] = (df & 0x80000000u) != 0;
             sv[u] = (dh[u] != 0.0 && (df & 0x80000000u))
                         ? (T)((a.d * dh[u]) * (1.0 / (double)(df & 0x7fffffffu)))
                         : (T)0;
@@ -686,7 +695,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             if (i < cnt) {
                 const T v = Fl[i];
                 F[base + i] = v;
-                if (sv[u] != (T)0) Snext[base + i] = sv[u];
+                if (rm[u]) Snext[base + i] = sv[u];
                 if ((threadIdx.x & (WAVE - 1)) == 0) Sbnext[(base + i) >> 6] = bits;
                 if (dh[u] != 0.0) a.H[base + i] = hv[u] + dh[u];
                 Rd += fabs((double)v);
@@ -779,7 +788,7 @@ struct FinArgs {
     DevCtl *ctl;
     const u64 *partR, *partC;
     i64 nR, nC;  // slots written by the step's kernels (0: none)
-    double d, theta, tol, n_d, zsum;
+    double d, theta, tol, n_d, zsum, dense_at;
     int K, mode, normalized;
 };
 
@@ -829,6 +838,9 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinArgs a) {
         c->sweep += 1;
         c->parity ^= 1;
         c->fcount_last = c->fcount;
+        // most cross-range entries carried fluid this sweep: the next one reads every
+        // in-flight value directly (a bitmap test would cost a random read of its own)
+        c->dense = a.mode == FIN_DI && a.dense_at > 0.0 && (double)remote >= a.dense_at;
     }
     double bound;
     if (a.mode == FIN_ADJ || a.mode == FIN_ADJ_INIT) bound = mx / (1.0 - a.d);
@@ -859,6 +871,7 @@ int launch_finalize(DevCtl *ctl, const SweepParams &p, int mode, hipStream_t st,
     a.tol = p.tol;
     a.n_d = (double)p.n;
     a.zsum = p.zsum;
+    a.dense_at = p.dense_at;
     a.K = p.K;
     a.mode = mode;
     a.normalized = p.normalized;
