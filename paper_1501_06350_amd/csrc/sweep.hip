@@ -49,6 +49,16 @@ __device__ __forceinline__ int wave_incl_scan_dpp(int v) {
     return v;
 }
 
+// 1/c for an integer count c >= 1: the hardware estimate refined by two Newton steps
+// (within an ulp of the correctly rounded quotient; no scaling is needed in this range)
+__device__ __forceinline__ double recip_count(unsigned c) {
+    const double x = (double)c;
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -566,7 +576,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             const T v = lds_load(&Fl[ii]);
             const unsigned deg = Deg[ii] & 0x7fffffffu;
             const unsigned o0 = Off[ii], o1 = Off[ii + 1];
-            const double rdeg = 1.0 / (double)(deg ? deg : 1u);
+            const double rdeg = recip_count(deg ? deg : 1u);
             double f = 0.0;
             if (own && v != (T)0 && fabs((double)v) >= thr) {
                 f = (double)v;
@@ -577,8 +587,9 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             int dg = 0;
             unsigned st = 0;
             double q = 0.0;
+            // the history increment is read here and stored at the end of the chunk
+            const T dl0 = f != 0.0 ? Dl[i] : (T)0;
             if (f != 0.0) {
-                Dl[i] = (T)((double)Dl[i] + f);
                 if (deg == 0) {
                     Ld += fabs(f);
                 } else {
@@ -595,6 +606,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             const int inc = wave_incl_scan_dpp(dg);
             const int total = __builtin_amdgcn_readlane(inc, WAVE - 1);
             edges += (lane == 0) ? (u64)total : 0ull;
+            if (f != 0.0) Dl[i] = (T)((double)dl0 + f);
             if (total == 0) continue;
             const int rk = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(pm >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((unsigned)pm, 0u));
