@@ -448,6 +448,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     unsigned *sc_bits = sc_bits_all + w * (BLD2_SLOTS / 32);
     __shared__ u64 red[PSC * 16];
     __shared__ int bad;
+    __shared__ int chunk_ctr[64];  // chunks handed out in each local round
 
     const int par = ctl->parity;
     const T *Sprev = reinterpret_cast<const T *>(par ? a.S1 : a.S0);
@@ -466,6 +467,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     const int nloc = (int)(a.loc_base[r + 1] - lb);
     const int ncap = min(nloc, a.tcap);
     if (threadIdx.x == 0) bad = 0;
+    if (threadIdx.x < 64) chunk_ctr[threadIdx.x] = 0;
     for (int wd = threadIdx.x; wd < nw * (BLD2_SLOTS / 32); wd += nthr) sc_bits_all[wd] = 0u;
 
     // 1. stage the range; every loop keeps SU independent loads in flight per thread
@@ -556,9 +558,13 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     }
     __syncthreads();
 
-    // 3. local rounds (LDS only); wave w owns [my0, my1)
-    const int sub = (((cnt + nw - 1) / nw) + WAVE - 1) & ~(WAVE - 1);
-    const int my0 = w * sub, my1 = min(cnt, my0 + sub);
+    // 3. local rounds (LDS only).  The waves take the range's 64-node chunks from a
+    // per-round counter (the next index is requested while a chunk runs), so waves with
+    // light chunks take more of them.  Waves run their rounds independently: a wave may
+    // reach a chunk that another wave still handles in an earlier round; both then take
+    // the same fluid value, which the atomic history update keeps exact (the node is
+    // left with the negative of that value, diffused later like any other fluid).
+    const int nch = (cnt + WAVE - 1) / WAVE;
     double Ld = 0.0;  // this lane's leak, added to the exact sum once at the end
     u64 nodes = 0, edges = 0;
     for (int round = 0; round < rounds; ++round) {
@@ -566,10 +572,16 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
         // nodes taken in this round are listed across the wave's chunks and their edges
         // pushed together once the list is full: ln nodes, ltot edge slots (wave-uniform)
         int ln = 0, ltot = 0;
-        for (int c = my0; c < my1; c += WAVE) {
+        int nxt = 0;
+        if (lane == 0) nxt = atomicAdd(&chunk_ctr[round], 1);
+        for (;;) {
+            const int ch = __builtin_amdgcn_readfirstlane(nxt);
+            if (ch >= nch) break;
+            if (lane == 0) nxt = atomicAdd(&chunk_ctr[round], 1);
+            const int c = ch * WAVE;
             const int i = c + lane;
-            const bool own = i < my1;
-            const int ii = own ? i : my0;  // lanes past the share load the first node
+            const bool own = i < cnt;
+            const int ii = own ? i : c;  // lanes past the range load the chunk's first node
             // the node's degree, offsets and 1/degree load and compute while its fluid
             // value is read; a taken node gives up exactly the value read (a subtraction
             // without return), so fluid that reached it in the meantime stays
@@ -587,9 +599,8 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             int dg = 0;
             unsigned st = 0;
             double q = 0.0;
-            // the history increment is read here and stored at the end of the chunk
-            const T dl0 = f != 0.0 ? Dl[i] : (T)0;
             if (f != 0.0) {
+                atomicAdd(&Dl[i], (T)f);
                 if (deg == 0) {
                     Ld += fabs(f);
                 } else {
@@ -606,7 +617,6 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             const int inc = wave_incl_scan_dpp(dg);
             const int total = __builtin_amdgcn_readlane(inc, WAVE - 1);
             edges += (lane == 0) ? (u64)total : 0ull;
-            if (f != 0.0) Dl[i] = (T)((double)dl0 + f);
             if (total == 0) continue;
             const int rk = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(pm >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((unsigned)pm, 0u));
