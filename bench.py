@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--range-log2", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=6,
                     help="block-local rounds per sweep on the 50M graph (0: the library's default, 4)")
-    ap.add_argument("--theta", type=float, default=0.3,
+    ap.add_argument("--theta", type=float, default=0.2,
                     help="frontier scale of the sweeps (1.0 = the paper's at-least-average rule; also reported)")
     ap.add_argument("--range-cut", type=int, default=0, help="range_cut option (-1: ranges at multiples of 2^rb)")
     ap.add_argument("--traffic-probe", action="store_true",

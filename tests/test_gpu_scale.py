@@ -4,7 +4,7 @@ webgen(1M, 2): the library's D-Iteration and power iteration against the oracle'
 synchronous D-Iteration run to a certified 1e-11, element by element (|dx|_1 <= 1e-9 |x|_1
 with double arithmetic, <= 1e-6 |x|_1 with float fluid or float x/s).
 
-webgen(50M, 3), the headline configuration (frontier scale 0.3, other options default, tol
+webgen(50M, 3), the headline configuration (frontier scale 0.2, 6 local rounds, tol
 1e-8, double fluid and float fluid): the oracle recomputes, in double, the exact residual F = F_0 + d P H - H of the
 history the library returns, over all rows and row by row on a sample, and checks the
 certificate |x - H|_1 <= |F|_1 / (1-d) <= tol (Theorem 1) without the library's own residual;
@@ -70,7 +70,7 @@ def test_headline_50m_certificate(gpu, web50m, fp32):
     say("webgen(50M, 3): n=%d m=%d, float fluid %d" % (g.n, g.m, fp32))
     Z = O.uniform_Z(g.n)
     F0 = (1 - D) * Z
-    with gpu.from_graph(g, d=D, fluid_fp32=fp32, theta=0.3) as s:
+    with gpu.from_graph(g, d=D, fluid_fp32=fp32, theta=0.2, inner_rounds=6) as s:
         st = s.diffuse(1e-8)
         assert st["converged"] and st["bound"] <= 1e-8
         H = s.read(gpu.H)
