@@ -561,9 +561,9 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     // 3. local rounds (LDS only).  The waves take the range's 64-node chunks from a
     // per-round counter (the next index is requested while a chunk runs), so waves with
     // light chunks take more of them.  Waves run their rounds independently: a wave may
-    // reach a chunk that another wave still handles in an earlier round; both then take
-    // the same fluid value, which the atomic history update keeps exact (the node is
-    // left with the negative of that value, diffused later like any other fluid).
+    // reach a chunk that another wave still handles in an earlier round.  Takes are
+    // exchanges (the second wave finds only fluid that arrived after the first take, so
+    // the fluid stays nonnegative) and the history increment is an atomic add.
     const int nch = (cnt + WAVE - 1) / WAVE;
     double Ld = 0.0;  // this lane's leak, added to the exact sum once at the end
     u64 nodes = 0, edges = 0;
@@ -583,17 +583,13 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             const bool own = i < cnt;
             const int ii = own ? i : c;  // lanes past the range load the chunk's first node
             // the node's degree, offsets and 1/degree load and compute while its fluid
-            // value is read; a taken node gives up exactly the value read (a subtraction
-            // without return), so fluid that reached it in the meantime stays
+            // value is read
             const T v = lds_load(&Fl[ii]);
             const unsigned deg = Deg[ii] & 0x7fffffffu;
             const unsigned o0 = Off[ii], o1 = Off[ii + 1];
             const double rdeg = recip_count(deg ? deg : 1u);
             double f = 0.0;
-            if (own && v != (T)0 && fabs((double)v) >= thr) {
-                f = (double)v;
-                atomicAdd(&Fl[i], -v);
-            }
+            if (own && v != (T)0 && fabs((double)v) >= thr) f = (double)atomicExch(&Fl[i], (T)0);
             if (__ballot(f != 0.0) == 0) continue;
             any = true;
             int dg = 0;

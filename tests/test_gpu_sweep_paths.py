@@ -12,8 +12,12 @@ in-flight values directly), scale 4 leaves most idle (the gather tests the bitma
 1, 6 and 12 local rounds; double and float fluid; cut-aligned and plain ranges.
 
 Checks: the solve converges; |H - x|_1 <= rel |x|_1 (x from the oracle's synchronous
-D-Iteration run to 1e-14), and within the certified bound (Theorem 1); the invariant
-H + F = F_0 + d P H (equation HnFn) with P applied by the oracle.
+D-Iteration run to 1e-14), and within the certified bound (Theorem 1); double fluid stays
+nonnegative (two waves may take from one node in different local rounds; float fluid is
+recomputed in double before the stop, a residual signed at the rounding level); mass balance
+sum F + (1-d) sum H + d l = (1-d) sum Z with the leak l the library reports (about 12% of
+the nodes are dangling); the invariant H + F = F_0 + d P H (equation HnFn) with P applied
+by the oracle.
 """
 import numpy as np
 import pytest
@@ -72,10 +76,15 @@ def test_local_round_paths(gpu, chunky, theta, rounds, fp32, cut):
         assert st["converged"]
         H = s.read(gpu.H)
         F = s.read(gpu.F)
+        leak = s.read(gpu.LEAKS)[0]
     err = float(np.abs(H - x).sum())
     say("  %d sweeps, bound %.3e, |H - x|_1 = %.3e" % (st["sweeps"], st["bound"], err))
     assert err <= rel * float(np.abs(x).sum())
     assert err <= st["bound"] * (1 + 1e-7) + 1e-14
+    if not fp32:
+        assert np.all(F >= 0)
+    defect = F.sum() + (1 - D) * H.sum() + D * leak - (1 - D) * Z.sum()
+    assert abs(defect) <= (1e-6 if fp32 else 1e-13)
     F0 = O.initial_fluid(D, Z, False)
     if fp32:
         assert O.invariant_residual_l1(og, D, F0, H, F) <= 1e-7 * st["residual"] + 1e-15
