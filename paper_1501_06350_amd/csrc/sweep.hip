@@ -352,7 +352,7 @@ struct Bld2Args {
 };
 
 // LDS layout of k_bld2_sweep (bytes): F[B], dH[B] (fluid type), deg[B], off[B+1] (u32),
-// padding to 8, then per wave 64 x (q double, start u32, offset i32), per wave a bitmap of
+// padding to 8, then per wave 64 x (q double, start u32), per wave a bitmap of
 // BLD2_SLOTS bits, then the targets.
 __host__ __device__ inline size_t bld2_scratch_offset(int B, int tsize) {
     return ((size_t)2 * B * tsize + (size_t)4 * (2 * B + 1) + 7) & ~(size_t)7;
@@ -363,7 +363,7 @@ constexpr int BLD2_SLOTS = 1024;
 
 size_t bld2_fixed_lds(int rb, int fp32, int threads) {
     return bld2_scratch_offset(1 << rb, fp32 ? 4 : 8) +
-           (size_t)(threads / WAVE) * (WAVE * (8 + 4 + 4) + BLD2_SLOTS / 8);
+           (size_t)(threads / WAVE) * (WAVE * (8 + 4) + BLD2_SLOTS / 8);
 }
 
 // Pushes the local edges of the nodes a wave has listed: listed node k sends sc_q[k] along
@@ -439,12 +439,10 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     unsigned *Off = Deg + B;  // B + 1 entries
     double *sc_q_all = reinterpret_cast<double *>(smem + bld2_scratch_offset(B, (int)sizeof(T)));
     unsigned *sc_start_all = reinterpret_cast<unsigned *>(sc_q_all + nw * WAVE);
-    int *sc_off_all = reinterpret_cast<int *>(sc_start_all + nw * WAVE);
-    unsigned *sc_bits_all = reinterpret_cast<unsigned *>(sc_off_all + nw * WAVE);
+    unsigned *sc_bits_all = sc_start_all + nw * WAVE;
     unsigned short *Tg = reinterpret_cast<unsigned short *>(sc_bits_all + nw * (BLD2_SLOTS / 32));
     double *sc_q = sc_q_all + w * WAVE;
     unsigned *sc_start = sc_start_all + w * WAVE;
-    int *sc_off = sc_off_all + w * WAVE;
     unsigned *sc_bits = sc_bits_all + w * (BLD2_SLOTS / 32);
     __shared__ u64 red[PSC * 16];
     __shared__ int bad;
@@ -633,45 +631,28 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                 ltot += total;
                 continue;
             }
-            // a chunk with more edge slots than a list holds: its own pass, the slot's node
-            // found by binary search over the chunk's nact nodes
-            if (dg > 0) {
-                sc_start[rk] = st;
-                sc_off[rk] = inc - dg;
-                sc_q[rk] = q;
-            }
-            wave_sync_lds();
-            const int depth = nact > 1 ? 32 - __builtin_clz((unsigned)(nact - 1)) : 0;
-            constexpr int EDGE_U = 4;
-            for (int sb = lane; sb < total; sb += WAVE * EDGE_U) {
-                unsigned tgt[EDGE_U];
-                double val[EDGE_U];
-#pragma unroll
-                for (int u = 0; u < EDGE_U; ++u) {
-                    const int sl = min(sb + u * WAVE, total - 1);
-                    int lo = 0, hi = nact - 1;  // last listed node k with sc_off[k] <= sl
-                    for (int it = 0; it < depth; ++it) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        const bool le = sc_off[mid] <= sl;
-                        lo = le ? mid : lo;
-                        hi = le ? hi : mid - 1;
-                    }
-                    const unsigned pp = sc_start[lo] + (unsigned)(sl - sc_off[lo]);
+            // a chunk with more edge slots than a list holds (rare): its nodes push one at a
+            // time, the whole wave striding over the node's local edges
+            const long long qb = __double_as_longlong(q);
+            for (u64 pend = pm; pend != 0; pend &= pend - 1) {
+                const int src = __builtin_ctzll(pend);
+                const unsigned st_n = (unsigned)__builtin_amdgcn_readlane((int)st, src);
+                const int dg_n = __builtin_amdgcn_readlane(dg, src);
+                const unsigned q_lo = (unsigned)__builtin_amdgcn_readlane((int)qb, src);
+                const int q_hi = __builtin_amdgcn_readlane((int)(qb >> 32), src);
+                const T val = (T)__longlong_as_double(((long long)q_hi << 32) | (long long)q_lo);
+                for (int e = lane; e < dg_n; e += WAVE) {
+                    const int pp = (int)st_n + e;
                     unsigned t;
-                    if ((int)pp < ncap) {
+                    if (pp < ncap) {
                         t = Tg[tdelta + pp];
                     } else {
-                        t = a.loc_tgt[lb + min((int)pp, nloc - 1)];
+                        t = a.loc_tgt[lb + min(pp, nloc - 1)];
                         asm volatile("" : "+v"(t));
                     }
-                    tgt[u] = t;
-                    val[u] = sc_q[lo];
+                    atomicAdd(&Fl[t], val);
                 }
-#pragma unroll
-                for (int u = 0; u < EDGE_U; ++u)
-                    if (sb + u * WAVE < total) atomicAdd(&Fl[tgt[u]], (T)val[u]);
             }
-            wave_sync_lds();
         }
         if (ltot > 0)
             bld2_push_list<T>(Fl, Tg, tdelta, ncap, nloc, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start), sc_q,
