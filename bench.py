@@ -127,8 +127,8 @@ def main():
                     help="for profiling: run only the k=64, 256-graph and adjoint legs and print their figures")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: every box here has a single MI355X, and the multi-GPU "
-              "partitioning of the sweep is a design note, not a measured path.", file=sys.stderr)
+        print("bench.py measures one GPU only: the multi-GPU partitioning of the sweep is a design "
+              "note, not a built path.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
