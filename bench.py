@@ -330,10 +330,10 @@ def _timed(fn):
 
 def bench_batched(fp32):
     """Personalized PageRank, webgen(4M, seed 4), k=64 columns of 16 seeds each, L1 tol 1e-8
-    per column: one k=64 tile solve (float fluid, the tile's precision, theta 1: its best) vs
-    64 single-column solves on the same resident graph (di_set_z between them, outside the
-    timed calls) in float and double fluid at theta 1 and 0.5; the speedup is taken against
-    the fastest of the four."""
+    per column: one k=64 tile solve (float fluid, the tile's precision, theta 1 with 4 rounds:
+    its best) vs 64 single-column solves on the same resident graph (di_set_z between them,
+    outside the timed calls) in float and double fluid with (theta, rounds) = (1, 4), (0.5, 4)
+    and (0.2, 6); the speedup is taken against the fastest of the six."""
     import numpy as np
     import workloads as W
     from paper_1501_06350_amd import binding as B
@@ -342,16 +342,17 @@ def bench_batched(fp32):
     out = {"workload": "webgen n=%d m=%d seed=4, k=64 x 16 seeds, f32 fluid tile" % (g.n, g.m)}
     singles = {}
     for prec in ("f32", "f64"):
-        for th in (1.0, 0.5):
+        for th, rr in ((1.0, 4), (0.5, 4), (0.2, 6)):
             total, sweeps = 0.0, 0
-            with B.from_graph(g, d=D, Z=np.ascontiguousarray(Z[:, 0]), fluid_fp32=prec == "f32", theta=th) as sc:
+            with B.from_graph(g, d=D, Z=np.ascontiguousarray(Z[:, 0]), fluid_fp32=prec == "f32", theta=th,
+                              inner_rounds=rr) as sc:
                 sc.diffuse(TOL)  # warm-up
                 for c in range(64):
                     sc.set_z(np.ascontiguousarray(Z[:, c]))
                     st, ms = _timed(lambda: sc.diffuse(TOL))
                     total += ms
                     sweeps += st["sweeps"]
-            key = "%s_theta%g" % (prec, th)
+            key = "%s_theta%g_r%d" % (prec, th, rr)
             singles[key] = (total, sweeps / 64)
             out["single_%s_total_ms" % key] = round(total, 3)
             out["single_%s_mean_sweeps" % key] = round(sweeps / 64, 2)
@@ -365,7 +366,7 @@ def bench_batched(fp32):
         assert st["converged"]
     out["batched_ms"] = round(ms, 3)
     out["speedup"] = round(best / ms, 3)
-    out["speedup_same_precision"] = round(singles["%s_theta1" % ("f32" if fp32 else "f64")][0] / ms, 3)
+    out["speedup_same_precision"] = round(singles["%s_theta1_r4" % ("f32" if fp32 else "f64")][0] / ms, 3)
     out["batched_sweeps"] = st["sweeps"]
     out["edge_column_updates"] = st["edge_updates"]
     out["geups_edge_columns"] = round(st["edge_updates"] / (ms * 1e-3) / 1e9, 3)
