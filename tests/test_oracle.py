@@ -154,6 +154,64 @@ def test_transpose_matches_stable_argsort():
     np.testing.assert_array_equal(og.in_ptr, np.concatenate([[0], np.cumsum(cnt)]))
 
 
+def _product_graphs():
+    """Weighted and unweighted graphs with dangling nodes, self-loops and repeated edges."""
+    out = []
+    for weighted in (False, True):
+        g = random_graph(300, 21 + weighted, weighted=weighted, p_dangling=0.25)
+        src = np.repeat(np.arange(g.n), np.diff(g.out_ptr))
+        assert (src == g.out_idx).any(), "the graph must hold a self-loop"
+        pairs = src.astype(np.int64) * g.n + g.out_idx
+        assert len(np.unique(pairs)) < len(pairs), "the graph must hold a repeated edge"
+        assert (np.diff(g.out_ptr) == 0).any()
+        out.append(g)
+    # a graph with a hub receiving most edges (long IN row)
+    rng = np.random.default_rng(5)
+    src = np.repeat(np.arange(400), rng.integers(0, 6, size=400))
+    dst = np.where(rng.random(len(src)) < 0.6, 7, rng.integers(0, 400, size=len(src)))
+    out.append(W.from_edges(400, src, dst, rng.lognormal(0.0, 1.0, len(src)).astype(np.float32), "hub"))
+    return out
+
+
+@pytest.mark.parametrize("gi", [0, 1, 2])
+def test_sparse_product_matches_dense_P(gi):
+    """OGraph.P_times / P_times_rows (the checkers of the large-graph certificates) against
+    P assembled here with numpy from the edge list (equation def-p)."""
+    g = _product_graphs()[gi]
+    og = O.OGraph.of(g)
+    P = P_numpy(g)
+    rng = np.random.default_rng(30 + gi)
+    # two sums of the same terms in different orders differ by at most about
+    # 2 (row length) eps times the sum of |terms|
+    tol_rows = 2.0 * (np.diff(og.in_ptr) + 1) * np.finfo(float).eps
+    for v in (rng.random(g.n), rng.standard_normal(g.n), np.eye(g.n)[3], np.ones(g.n)):
+        ref = P @ v
+        scale = np.abs(P) @ np.abs(v)
+        assert np.all(np.abs(og.P_times(v) - ref) <= tol_rows * scale)
+        rows = np.sort(rng.choice(g.n, size=60, replace=False))
+        np.testing.assert_array_equal(og.P_times_rows(rows, v), og.P_times(v)[rows])
+        assert np.all(np.abs(og.P_times_rows(rows, v) - ref[rows]) <= tol_rows[rows] * scale[rows])
+    # column sums: 1 for every non-dangling column, 0 for a dangling one (Section 2.1)
+    colsum = np.array([og.P_times(e).sum() for e in np.eye(g.n)[:50]])
+    dang = np.diff(g.out_ptr)[:50] == 0
+    np.testing.assert_allclose(colsum[~dang], 1.0, atol=1e-14)
+    assert (colsum[dang] == 0.0).all()
+
+
+def test_sparse_product_pin_detects_target_scaling():
+    """Planted mistake: scaling each entry by 1/s of the target instead of the source must
+    fail the comparison the pin above makes."""
+    g = _product_graphs()[1]
+    og = O.OGraph.of(g)
+    v = np.random.default_rng(40).random(g.n)
+    src = np.repeat(np.arange(g.n), np.diff(g.out_ptr))
+    # y_i = sum over edges j -> i of w_e / s_i * v_j (the mutated oracle formula)
+    bad = np.zeros(g.n)
+    np.add.at(bad, g.out_idx, g.w.astype(np.float64) * og.inv_s[g.out_idx] * v[src])
+    assert np.abs(bad - P_numpy(g) @ v).max() > 1e-3
+    assert np.abs(og.P_times(v) - P_numpy(g) @ v).max() < 1e-13
+
+
 def test_inv_s_left_fold():
     g = random_graph(50, 7, weighted=True)
     og = O.OGraph.of(g)
