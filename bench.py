@@ -57,18 +57,43 @@ def time_di(s, steps, warmup, n, m):
          "device_ms": sum(x["ms"] for x in stats) / steps, "bound": stats[-1]["bound"],
          "kern_ns": kern_ns, "kern_launch": kern_launch, "local_pushes": local_pushes}
     r["geups"] = r["edges"] / (ms * 1e-3) / 1e9
-    # roofline of the block-local sweep: the byte model of the design doc, per launch
     T = 4 if s.fluid_fp32 else 8
-    per_sweep = n * 3 * T + s.info(B.INFO_M_REMOTE) * (6 + T) + s.info(B.INFO_NRANGES) * 16
-    alg = r["sweeps"] * steps * per_sweep + r["diffusions"] * steps * 48 + local_pushes * 2
     r["avg_ns"] = kern_ns / max(kern_launch, 1)
+    # roofline of the block-local sweep kernel, per launch, in two byte models:
+    # (1) the method's algorithmic bytes of a push sweep: per edge update 4 (index) + 2T
+    #     (read and write of F_j), per diffusion 2*4 (row offsets) + 2T (own fluid) + 16
+    #     (H read and write) + 2*4 (frontier index) = 28 + 2T, per sweep T*n (scan of F),
+    #     i.e. 20 B / 44 B / 8n B in double and 12 B / 36 B / 4n B in float;
+    # (2) the bytes this kernel's design must move: per sweep 3 n_int T (F read and written,
+    #     in-flight values written) + m_rem (6 + T) (cross-range entry and in-flight gather)
+    #     + 16 per range, per diffusion 48 (H, 1/s, cross-range weight, offsets), per local
+    #     push 2 (staged target); local pushes stay in LDS
+    alg = r["edges"] * steps * (4 + 2 * T) + r["diffusions"] * steps * (28 + 2 * T) + r["sweeps"] * steps * n * T
     r["bytes_per_launch"] = alg / max(kern_launch, 1)
     r["achieved"] = r["bytes_per_launch"] / r["avg_ns"]  # GB/s
+    n_int = s.info(B.INFO_N_INTERNAL)
+    per_sweep = n_int * 3 * T + s.info(B.INFO_M_REMOTE) * (6 + T) + s.info(B.INFO_NRANGES) * 16
+    design = r["sweeps"] * steps * per_sweep + r["diffusions"] * steps * 48 + local_pushes * 2
+    r["design_bytes_per_launch"] = design / max(kern_launch, 1)
+    r["design_achieved"] = r["design_bytes_per_launch"] / r["avg_ns"]
     log("DI (%s fluid): %.2f ms/solve (device %.2f ms), sweeps %.1f, edge updates %.3e, rounds %.2f, GEUPS %.1f; "
-        "sweep kernel %d launches, avg %.1f us, %.3f GB/launch -> %.0f GB/s" %
+        "sweep kernel %d launches, avg %.1f us, %.3f GB/launch -> %.0f GB/s (design model %.3f GB -> %.0f GB/s)" %
         ("f32" if T == 4 else "f64", ms, r["device_ms"], r["sweeps"], r["edges"], r["edges"] / m, r["geups"],
-         kern_launch, r["avg_ns"] / 1e3, r["bytes_per_launch"] / 1e9, r["achieved"]))
+         kern_launch, r["avg_ns"] / 1e3, r["bytes_per_launch"] / 1e9, r["achieved"],
+         r["design_bytes_per_launch"] / 1e9, r["design_achieved"]))
     return r
+
+
+def sweep_roofline(r, kernel, traffic=None):
+    """roofline object of the block-local sweep kernel from time_di's figures"""
+    return roofline(r["achieved"], traffic=traffic, kernel=kernel, launches=r["kern_launch"],
+                    avg_us=round(r["avg_ns"] / 1e3, 2), bytes_per_launch=round(r["bytes_per_launch"]),
+                    model="push sweep: 4+2T B per edge update, 28+2T B per diffusion, T*n B per sweep",
+                    design_model={"bytes_per_launch": round(r["design_bytes_per_launch"]),
+                                  "achieved": round(r["design_achieved"], 1),
+                                  "frac": round(r["design_achieved"] / HBM_PEAK_GBS, 4),
+                                  "model": "3 n_int T + m_rem (6+T) + 16 per range per sweep, 48 B per "
+                                           "diffusion, 2 B per local push (local pushes stay in LDS)"})
 
 
 def time_pi(s, steps, n, m):
@@ -114,7 +139,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the k=64, 256-graph and adjoint legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f32-leg", action="store_true", help="skip the float-fluid D-Iteration leg")
-    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--cpu-sweeps", type=int, default=3, help="synchronous sweeps of the oracle's DI (one thread)")
+    ap.add_argument("--cpu-pi-iters", type=int, default=12, help="power iterations of the oracle (all threads)")
     ap.add_argument("--range-log2", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=6,
                     help="block-local rounds per sweep on the 50M graph (0: the library's default, 4)")
@@ -197,10 +223,9 @@ def main():
         "pi": {"x_over_s": "f64", "iterations": pi["iterations"], "geups": round(pi["geups"], 3),
                "l1_diff_to_di": di_pi_l1, "roofline": roofline(pi["achieved"])},
         "di_pi_l1_diff": di_pi_l1,
-        "roofline": roofline(di["achieved"],
-                             traffic=measured_traffic("f32" if fp32 else "f64", args.theta, args.range_cut, used_rounds),
-                             kernel="k_bld2_sweep<%s>" % ("float" if fp32 else "double"),
-                             launches=di["kern_launch"], avg_us=round(di["avg_ns"] / 1e3, 2)),
+        "roofline": sweep_roofline(di, "k_bld2_sweep<%s>" % ("float" if fp32 else "double"),
+                                   measured_traffic("f32" if fp32 else "f64", args.theta, args.range_cut,
+                                                    used_rounds)),
     }
 
     # the paper's frontier rule (theta = 1: at least the average fluid), same precision
@@ -228,8 +253,7 @@ def main():
         leg = {"ms": round(d2["ms"], 3), "sweeps": d2["sweeps"], "edge_updates": d2["edges"],
                "geups": round(d2["geups"], 3), "bound": d2["bound"],
                "l1_diff_to_headline_di": float(np.abs(x2 - xd).sum()),
-               "roofline": roofline(d2["achieved"], kernel="k_bld2_sweep<%s>" % ("double" if fp32 else "float"),
-                                    launches=d2["kern_launch"], avg_us=round(d2["avg_ns"] / 1e3, 2))}
+               "roofline": sweep_roofline(d2, "k_bld2_sweep<%s>" % ("double" if fp32 else "float"))}
         result["di_%s_fluid" % ("f64" if fp32 else "f32")] = leg
         if p2 is not None:
             l1 = float(np.abs(xd - p2.pop("x")).sum())
@@ -251,7 +275,13 @@ def main():
             log("%s: %s" % (key, json.dumps(result[key])))
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(g, args.cpu_sweeps)
+        try:
+            det = deterministic_solve(g)
+            result["di_deterministic"] = det
+        except Exception as e:
+            det = None
+            result["di_deterministic"] = {"error": str(e)[:300]}
+        result["cpu_baseline"] = cpu_baseline(g, pi["iterations"], args.cpu_pi_iters, args.cpu_sweeps, det)
     print(json.dumps(result), flush=True)
 
 
@@ -459,20 +489,73 @@ def bench_adjoint():
     return out
 
 
-def cpu_baseline(g, sweeps):
-    """The oracle's synchronous sweep on the same graph, a bounded number of sweeps."""
+def host_cpu():
+    """(model name, threads this process may run on) of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(g, pi_iters, pi_sample, di_sweeps, di_det):
+    """The oracle on the host cores, on bounded samples of the headline solve:
+    Jacobi power iteration (its OpenMP row loop, every thread the process has) for
+    `pi_sample` iterations, and its synchronous D-Iteration (one thread) for `di_sweeps`
+    sweeps.  Time to the 1e-8 certificate is extrapolated: power iteration needs `pi_iters`
+    iterations (the GPU's double power iteration, the same arithmetic), synchronous
+    D-Iteration the edge updates of the GPU's deterministic solve (`di_det`, bit-identical
+    to the oracle's sweep) at the sampled rate."""
     import oracle as O
     t0 = time.time()
     og = O.OGraph.of(g)
     log("oracle graph build %.1fs" % (time.time() - t0))
-    y = O.SyncDI(og, D, O.uniform_Z(g.n), fluid_fp32=False)
+    model, avail = host_cpu()
+    threads = O.num_threads()
+    Z = O.uniform_Z(g.n)
     t = time.perf_counter()
-    y.run(TOL, max_sweeps=sweeps)
-    dt = time.perf_counter() - t
+    O.power(og, D, Z, tol=1e-300, max_iters=pi_sample)
+    dt_pi = time.perf_counter() - t
+    per_iter = dt_pi / pi_sample
+    pi_geups = pi_sample * g.m / dt_pi / 1e9
+    y = O.SyncDI(og, D, Z, fluid_fp32=False)
+    t = time.perf_counter()
+    y.run(TOL, max_sweeps=di_sweeps)
+    dt_di = time.perf_counter() - t
     edges = sum(tr[2] for tr in y.trace)
-    return {"value": round(edges / dt / 1e9, 5), "unit": "GEUPS", "cores": 1, "kind": "oracle",
-            "sample": "first %d synchronous sweeps of the oracle's D-Iteration (double) on the same "
-                      "webgen graph, %.3e edge updates in %.1f s" % (sweeps, edges, dt)}
+    di_geups = edges / dt_di / 1e9
+    out = {"value": round(pi_geups, 5), "unit": "GEUPS", "cores": threads, "kind": "oracle",
+           "sample": "%d Jacobi power iterations of the oracle (double, OpenMP rows, %d threads) on the same "
+                     "webgen graph, %.3e edge updates in %.1f s" % (pi_sample, threads, pi_sample * g.m, dt_pi),
+           "cpu_model": model, "threads_available": avail,
+           "pi_time_to_tol_ms": round(1e3 * per_iter * pi_iters, 1),
+           "pi_time_to_tol_basis": "%d iterations x %.1f ms per iteration" % (pi_iters, 1e3 * per_iter),
+           "di_sync_1thread": {"geups": round(di_geups, 5), "sample": "first %d synchronous sweeps, %.3e edge "
+                               "updates in %.1f s" % (di_sweeps, edges, dt_di)}}
+    if di_det is not None:
+        out["di_sync_1thread"]["time_to_tol_ms"] = round(1e3 * di_det["edges"] / (di_geups * 1e9), 1)
+        out["di_sync_1thread"]["time_to_tol_basis"] = (
+            "%.4e edge updates in %d sweeps (the deterministic GPU solve) at the sampled rate" %
+            (di_det["edges"], di_det["sweeps"]))
+    return out
+
+
+def deterministic_solve(g):
+    """The deterministic synchronous sweep (the oracle's sweep, bit for bit) to TOL on the
+    GPU: its sweep and edge-update counts."""
+    from paper_1501_06350_amd import binding as B
+    with B.from_graph(g, d=D, deterministic=True) as s:
+        st, ms = _timed(lambda: s.diffuse(TOL))
+    log("deterministic DI: %d sweeps, %.4e edge updates, %.1f ms" % (st["sweeps"], st["edge_updates"], ms))
+    return {"sweeps": st["sweeps"], "edges": st["edge_updates"], "ms": round(ms, 3)}
 
 
 if __name__ == "__main__":

@@ -136,6 +136,14 @@ typedef struct {
                               adjoint: max|F| / (1-d) */
     double bound_norm;     /* residual / (1 - d - d l/|Z|_1): distance of the normalised result (Section 3.3) */
     double leak;           /* l: fluid diffused at dangling nodes (Section 3.3) */
+    double mass_defect;    /* di_diffuse: sum F + (1-d) sum H + d l - (1-d) sum Z, the mass
+                              balance that equation HnFn implies because the columns of P sum
+                              to 1 except at dangling nodes (Section 2.1); zero in exact
+                              arithmetic, so it measures the rounding injected by the pushes
+                              (with float fluid: the rounding of F to float).  Sums are exact
+                              fixed-point sums rounded once.  With k > 1 or n_graphs > 1: the
+                              per-column/graph value of largest magnitude (DI_MASS_DEFECTS
+                              reads them all).  0 after di_power and di_adjoint. */
     double ms;             /* device time of the call (HIP events on the context's stream) */
     int converged;         /* 1 if every column/graph met the tolerance */
 } di_stats;
@@ -202,6 +210,8 @@ int di_adjoint(di_ctx *ctx, const double *g, double tol_inf, double *dZ, double 
 #define DI_DONE_SWEEPS 12 /* per column (or graph): total sweep count at which it met the
                              tolerance of the last di_diffuse, -1 if it has not (int64, k or
                              n_graphs; a single-column solve gives 1 value) */
+#define DI_MASS_DEFECTS 13 /* per column (or graph) mass defect of the last di_diffuse (double,
+                              k or n_graphs; see di_stats.mass_defect) */
 /* Copy a result into dst (host if dst_on_device = 0, device otherwise). */
 int di_read(di_ctx *ctx, int what, void *dst, int dst_on_device);
 

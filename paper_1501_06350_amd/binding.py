@@ -19,7 +19,8 @@ DI_OK, DI_EINVAL, DI_ENOMEM, DI_EHIP, DI_ENOCONV, DI_ESTATE, DI_ENUMERIC = 0, -1
 STATUS_NAMES = {0: "DI_OK", -1: "DI_EINVAL", -2: "DI_ENOMEM", -3: "DI_EHIP", -4: "DI_ENOCONV", -5: "DI_ESTATE",
                 -6: "DI_ENUMERIC"}
 LOOP_STREAM, LOOP_GRAPH = 0, 1
-X_RAW, X_NORM, F, H, LAMBDA, X_PI, IN_PTR, IN_IDX, INV_S, FRONTIER, RESIDUALS, LEAKS, DONE_SWEEPS = range(13)
+X_RAW, X_NORM, F, H, LAMBDA, X_PI, IN_PTR, IN_IDX, INV_S, FRONTIER, RESIDUALS, LEAKS, DONE_SWEEPS, \
+    MASS_DEFECTS = range(14)
 INFO_N, INFO_M, INFO_K, INFO_M_LOCAL, INFO_RANGE_LOG2, INFO_INNER_ROUNDS, INFO_FIXED_K, INFO_TOTAL_SWEEPS, \
     INFO_DEVICE_BYTES, INFO_KERNEL_NS, INFO_KERNEL_LAUNCHES, INFO_LOCAL_PUSHES, INFO_REMOTE_UPDATES, INFO_M_REMOTE, \
     INFO_NRANGES, INFO_N_INTERNAL = range(16)
@@ -50,7 +51,8 @@ class DiOpts(ctypes.Structure):
 class DiStats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("edge_updates", ctypes.c_int64), ("node_updates", ctypes.c_int64),
                 ("residual", ctypes.c_double), ("bound", ctypes.c_double), ("bound_norm", ctypes.c_double),
-                ("leak", ctypes.c_double), ("ms", ctypes.c_double), ("converged", ctypes.c_int)]
+                ("leak", ctypes.c_double), ("mass_defect", ctypes.c_double), ("ms", ctypes.c_double),
+                ("converged", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -223,7 +225,7 @@ class Solver:
             _check(self._lib.di_read(self._ctx, what, ctypes.c_void_p(buf.ctypes.data), 0))
             cnt = int(buf[:2].view(np.int64)[0])
             return buf[2:2 + cnt].copy()
-        elif what in (RESIDUALS, LEAKS):
+        elif what in (RESIDUALS, LEAKS, MASS_DEFECTS):
             shape, dt = (max(k, self.n_graphs),), np.float64
         elif what == DONE_SWEEPS:
             shape, dt = (max(k, self.n_graphs),), np.int64

@@ -19,6 +19,9 @@ int reset_batch(BatchState *b, const DevGraph &g, const SweepParams &p, hipStrea
 int set_batch_z(BatchState *b, const DevGraph &g, SweepParams &p, const double *Z, hipStream_t st);
 int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const di_opts &o, int spc, hipStream_t st,
                   di_stats *stats);
+// per-column mass balance sum F + (1-d) sum H + d l - (1-d) sum Z of the current state
+// (out: k host doubles)
+int batch_mass_defects(BatchState *b, const DevGraph &g, const SweepParams &p, double *out, hipStream_t st);
 int read_batch(BatchState *b, const DevGraph &g, const SweepParams &p, int what, void *dst, int on_device,
                hipStream_t st);
 i64 batch_sweeps(BatchState *b, hipStream_t st);

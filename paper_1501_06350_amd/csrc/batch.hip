@@ -85,6 +85,9 @@ struct BatchState {
     DlUnit *units = nullptr;     // delivery units over the cross-range in-entries
     i64 nunits = 0;
     int *rem_tgt_abs = nullptr;  // m_rem: absolute target row of each cross-range entry
+    // exact per-column sums of H (mass balance): limb slots and k doubles
+    u64 *partH = nullptr;
+    double *hsum = nullptr;
 };
 
 struct TileArgs {
@@ -971,7 +974,7 @@ void free_batch(BatchState *b) {
     if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
     void *ps[] = {b->F,   b->F0,      b->H,         b->snap,  b->ctl,         b->partR,
                   b->partC, b->partK, b->S,       b->fl,        b->blk_ptr, b->blk_ranges,
-                  b->units, b->rem_tgt_abs};
+                  b->units, b->rem_tgt_abs, b->partH, b->hsum};
     for (void *q : ps)
         if (q) (void)hipFree(q);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
@@ -1152,6 +1155,7 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
     if (!alloc(&b->F, n * k * T) || !alloc((void **)&b->F0, n * k * 8) || !alloc((void **)&b->H, n * k * 8) ||
         !alloc((void **)&b->ctl, sizeof(TileCtl)) || !alloc((void **)&b->partR, slots * KMAX * PSR * 8) ||
         !alloc((void **)&b->partC, slots * KMAX * 4 * 8) || !alloc((void **)&b->partK, slots * 2 * 8) ||
+        !alloc((void **)&b->partH, (size_t)b->gridR * KMAX * PSR * 8) || !alloc((void **)&b->hsum, KMAX * 8) ||
         (det && !alloc((void **)&b->snap, n * k * 8)))
         return fail(DI_ENOMEM);
     if (b->bld) {
@@ -1295,6 +1299,7 @@ int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const 
         stats->bound_norm = bn;
         stats->leak = lsum;
         stats->ms = ms;
+        stats->mass_defect = 0.0;
         stats->converged = all && !h.overflow;
     }
     if (h.overflow) {
@@ -1304,6 +1309,46 @@ int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const 
     if (!all) {
         set_error("sweep budget spent before every column met the tolerance");
         return DI_ENOCONV;
+    }
+    return DI_OK;
+}
+
+// One workgroup per column: add the column's limb slots of k_tile_reduce (run on H).
+__global__ void __launch_bounds__(256) k_tile_colsum(const u64 *__restrict__ part, int nslots, int K, double *out) {
+    __shared__ u64 red[4 * 4];
+    __shared__ u64 tot[4];
+    const int c = blockIdx.x;
+    u64 v[4] = {0, 0, 0, 0};
+    for (int q = threadIdx.x; q < nslots; q += blockDim.x)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] += part[((i64)q * KMAX + c) * PSR + t];
+    block_store_partials<4>(v, red, tot);
+    if (threadIdx.x == 0) out[c] = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], K);
+}
+
+int batch_mass_defects(BatchState *b, const DevGraph &g, const SweepParams &p, double *out, hipStream_t st) {
+    // the history of a column sums to at most |Z_c|_1 (x = (1-d)(I-dP)^{-1} Z_c, |P|_1 <= 1)
+    double zmax = 0.0;
+    for (int c = 0; c < b->k; ++c) zmax = std::max(zmax, b->zsum[c]);
+    int e_max = 0, e_n = 0;
+    std::frexp(zmax, &e_max);
+    while (((i64)1 << e_n) < b->n) ++e_n;
+    const int KH = 118 - (e_max + e_n);
+    TileArgs a = tile_args(b, g, p);
+    a.F = b->H;
+    a.K = KH;
+    a.partR = b->partH;
+    k_tile_reduce<double><<<b->gridR, TILE_THREADS, 0, st>>>(a, 1);
+    DI_LAUNCH_CHECK();
+    k_tile_colsum<<<b->k, 256, 0, st>>>(b->partH, b->gridR, KH, b->hsum);
+    DI_LAUNCH_CHECK();
+    std::vector<double> hs((size_t)b->k);
+    DI_HIP(hipMemcpyAsync(hs.data(), b->hsum, sizeof(double) * b->k, hipMemcpyDeviceToHost, st));
+    DI_TRY(sync_tile(b, st));
+    const TileCtl &h = *b->h_ctl;
+    for (int c = 0; c < b->k; ++c) {
+        const double l = limbs_to_double_raw(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
+        out[c] = h.R[c] + (1.0 - p.d) * hs[c] + p.d * l - (1.0 - p.d) * b->zsum[c];
     }
     return DI_OK;
 }

@@ -85,6 +85,8 @@ struct di_ctx {
     std::vector<hipEvent_t> tev;
     double kernel_ns = 0.0;
     i64 kernel_launches = 0;
+    // mass balance per column / graph after the last di_diffuse
+    std::vector<double> defects;
 };
 
 namespace {
@@ -308,6 +310,7 @@ void fill_stats(di_stats *st, const DevCtl &h, const DevCtl &before, double d, i
     st->leak = l;
     st->bound_norm = pi ? st->bound : h.R / (1.0 - d - d * l / zsum);
     st->ms = ms;
+    st->mass_defect = 0.0;
     st->converged = h.done && !h.overflow;
 }
 
@@ -355,6 +358,50 @@ int fill_stats_mg(di_ctx *c, di_stats *st, const DevCtl &h, const DevCtl &before
     st->bound = R / (1.0 - c->d);
     st->bound_norm = bn;
     st->leak = lsum;
+    return DI_OK;
+}
+
+// Mass balance of the current state per graph (one value for one graph), kept in
+// c->defects: sum F + (1-d) sum H + d l - (1-d) sum Z.  Equation HnFn gives
+// H + F = F_0 + d P H; summing its entries with 1^T P = 1^T - 1_D^T (the columns of P sum
+// to 1 except at dangling nodes, Section 2.1) leaves this sum at zero in exact
+// arithmetic.  sum F is the exact residual (fluid is nonnegative; in flight included),
+// sum H an exact fixed-point sum on the device; the stats get the largest magnitude.
+int mass_defects(di_ctx *c, di_stats *st) {
+    const i64 G = c->s.range_graph ? c->n_graphs : 1;
+    c->defects.assign((size_t)G, 0.0);
+    if (c->b) {
+        c->defects.resize((size_t)c->k);
+        DI_TRY(batch_mass_defects(c->b, c->g, c->p, c->defects.data(), c->st));
+    } else {
+        double zmax = c->zsum;
+        if (G > 1)
+            for (i64 q = 0; q < G; ++q) zmax = std::max(zmax, c->h_ginfo[q].zsum);
+        // every history sum is at most the sum of its Z (|P|_1 <= 1), so a fixed-point scale
+        // for n values of size zmax cannot overflow
+        const int KH = fixed_scale(zmax, c->g.n);
+        DI_TRY(launch_sum_history(c->g, c->s, KH, c->s.partH, c->s.hsum, c->st));
+        std::vector<double> hs((size_t)G);
+        DI_HIP(hipMemcpyAsync(hs.data(), c->s.hsum, sizeof(double) * G, hipMemcpyDeviceToHost, c->st));
+        DI_TRY(sync_ctl(c, c->s.ctl));
+        if (G > 1) {
+            DI_TRY(sync_gctl(c));
+            for (i64 q = 0; q < G; ++q) {
+                const GraphCtl &gc = c->h_gctl[q];
+                c->defects[q] = gc.R + (1.0 - c->d) * hs[q] + c->d * host_limbs(gc.limbsL, c->p.K) -
+                                (1.0 - c->d) * c->h_ginfo[q].zsum;
+            }
+        } else {
+            const DevCtl &h = *c->h_ctl;
+            c->defects[0] = h.R + (1.0 - c->d) * hs[0] + c->d * host_limbs(h.limbsL, c->p.K) - (1.0 - c->d) * c->zsum;
+        }
+    }
+    if (st) {
+        double v = 0.0;
+        for (double x : c->defects)
+            if (std::fabs(x) > std::fabs(v)) v = x;
+        st->mass_defect = v;
+    }
     return DI_OK;
 }
 
@@ -570,7 +617,7 @@ int di_destroy(di_ctx *c) {
     void *ps[] = {c->s.F, c->s.F0, c->s.H, c->s.S[0], c->s.S[1], c->s.snap, c->s.frontier, c->s.range_order,
                   c->s.ctl, c->s.X[0], c->s.X[1], c->s.XT[0], c->s.XT[1], c->s.pctl, c->s.Z, c->lam,
                   c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.range_cnt, c->d_seg_start, c->s.ginfo, c->s.gctl,
-                  c->d_gp, c->d_gs, c->d_gscale, c->ref_ht};
+                  c->d_gp, c->d_gs, c->d_gscale, c->ref_ht, c->s.partH, c->s.hsum};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     if (c->b) free_batch(c->b);
@@ -838,7 +885,9 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     // per-workgroup partial sums (see PSR / PSC)
     {
         const i64 slots = std::max<i64>(c->g.nranges, PART_MIN);
-        if ((rc = dalloc(c, &c->s.partR, slots * PSR)) || (rc = dalloc(c, &c->s.partC, slots * PSC))) return fail(rc);
+        if ((rc = dalloc(c, &c->s.partR, slots * PSR)) || (rc = dalloc(c, &c->s.partC, slots * PSC)) ||
+            (rc = dalloc(c, &c->s.partH, slots * PSR)) || (rc = dalloc(c, &c->s.hsum, std::max<i64>(opt.n_graphs, 1))))
+            return fail(rc);
     }
 
     // initial fluid F_0 = (1-d) Z, rounded to float in the float-fluid mode; fixed-point scale
@@ -873,11 +922,11 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     c->s.Sb[0] = reinterpret_cast<u64 *>(static_cast<char *>(c->s.S[0]) + s_vals);
     c->s.Sb[1] = reinterpret_cast<u64 *>(static_cast<char *>(c->s.S[1]) + s_vals);
     if (hipMemcpy(c->s.F0, f0.data(), n * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DI_EHIP);
-    if (Z && c->n_graphs == 1) {  // power iteration reads Z (one graph only)
+    // power iteration reads Z (one graph only), or (1-d)/n for a uniform Z
+    c->s.zc = (1.0 - d) * (1.0 / (double)n);
+    if (Z && c->n_graphs == 1) {
         if ((rc = dalloc(c, &c->s.Z, n))) return fail(rc);
         if (hipMemcpy(c->s.Z, Z, n * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DI_EHIP);
-    } else {
-        c->s.zc = (1.0 - d) * (1.0 / (double)n);
     }
     if (opt.deterministic) {
         if ((rc = dalloc(c, &c->s.snap, n)) || (rc = dalloc(c, &c->s.frontier, n))) return fail(rc);
@@ -916,6 +965,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
 
 int di_reset(di_ctx *c) {
     if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
+    c->defects.clear();
     if (c->b) return reset_batch(c->b, c->g, c->p, c->st);
     return reset_state(c);
 }
@@ -935,6 +985,7 @@ int di_set_z(di_ctx *c, const double *Z) {
             if (!(s > 0.0)) DI_FAIL(DI_EINVAL, "column %d of Z sums to zero", col);
         }
     }
+    c->defects.clear();
     if (c->b) return set_batch_z(c->b, c->g, c->p, Z, c->st);
     // layout of the context (padded per graph in a union), F_0 = (1-d) Z in double
     std::vector<double> f0((size_t)n, 0.0), gz((size_t)c->n_graphs, 0.0);
@@ -971,6 +1022,7 @@ int di_set_z(di_ctx *c, const double *Z) {
             (void)hipFree(c->s.Z);
             c->s.Z = nullptr;
         }
+        c->s.zc = (1.0 - c->d) * (1.0 / (double)n);  // read when s.Z is null (uniform Z)
     } else {
         for (i64 q = 0; q < c->n_graphs; ++q) c->h_ginfo[q].zsum = gz[q];
         DI_HIP(hipMemcpy(c->s.ginfo, c->h_ginfo.data(), sizeof(GraphInfo) * c->n_graphs, hipMemcpyHostToDevice));
@@ -993,6 +1045,11 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
     c->p.tol = tol;
     if (c->b) {
         int rc = diffuse_batch(c->b, c->g, c->p, c->o, c->spc, c->st, st);
+        if (rc == DI_OK || rc == DI_ENOCONV) {
+            const std::string msg = di_last_error();
+            DI_TRY(mass_defects(c, st));
+            if (rc != DI_OK) set_error("%s", msg.c_str());
+        }
         if (rc == DI_OK) c->forward_converged = true;
         return rc;
     }
@@ -1027,6 +1084,7 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
         DI_HIP(hipEventRecord(c->ev1, c->st));
         DI_HIP(hipEventSynchronize(c->ev1));
         DI_TRY(fill_stats_mg(c, st, before, before, 0.0f));
+        DI_TRY(mass_defects(c, st));
         c->forward_converged = true;
         return DI_OK;
     }
@@ -1038,6 +1096,7 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
             DI_HIP(hipEventSynchronize(c->ev1));
             fill_stats(st, before, before, c->d, c->p.K, 0.0f, false, c->zsum);
             if (st) st->converged = 1;
+            DI_TRY(mass_defects(c, st));
             c->forward_converged = true;
             return DI_OK;
         }
@@ -1084,6 +1143,7 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
     if (mg) DI_TRY(fill_stats_mg(c, st, h, before, ms));
     else fill_stats(st, h, before, c->d, c->p.K, ms, false, c->zsum);
     if (h.overflow) DI_FAIL(DI_ENUMERIC, "non-finite or out-of-range fluid in the residual");
+    DI_TRY(mass_defects(c, st));
     if (!h.done) {
         if (st) st->converged = 0;
         DI_FAIL(DI_ENOCONV, "sweep budget spent (%lld sweeps) before the tolerance", (long long)(h.sweep - before.sweep));
@@ -1299,6 +1359,10 @@ int read_union(di_ctx *c, int what, void *dst, int on_device) {
 int di_read(di_ctx *c, int what, void *dst, int on_device) {
     if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
     if (!dst) DI_FAIL(DI_EINVAL, "dst is NULL");
+    if (what == DI_MASS_DEFECTS) {
+        if (c->defects.empty()) DI_FAIL(DI_ESTATE, "no di_diffuse has run since the last reset");
+        return copy_small(c->defects.data(), sizeof(double) * c->defects.size(), dst, on_device);
+    }
     if (c->b) return read_batch(c->b, c->g, c->p, what, dst, on_device, c->st);
     if (c->s.range_graph) return read_union(c, what, dst, on_device);
     if (c->seg) {
@@ -1507,6 +1571,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         st->bound = h.maxF / (1.0 - c->d);
         st->bound_norm = st->bound;
         st->leak = 0.0;
+        st->mass_defect = 0.0;
         st->ms = ms;
         st->converged = h.done && !h.overflow;
     }
@@ -1569,6 +1634,7 @@ __global__ void k_ctl_restore(DevCtl *c, long long sweep, u64 l0, u64 l1, u64 l2
 }
 
 int di_load(di_ctx *c, const char *path) {
+    if (c) c->defects.clear();
     if (!c || !path) DI_FAIL(DI_EINVAL, "NULL argument");
     if (c->b || c->n_graphs > 1) DI_FAIL(DI_EINVAL, "checkpoints cover single right-hand-side solves on one graph");
     const i64 n = c->g.n;

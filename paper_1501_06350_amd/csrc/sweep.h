@@ -79,6 +79,9 @@ struct SolveState {
     GraphInfo *ginfo = nullptr;  // n_graphs
     GraphCtl *gctl = nullptr;    // n_graphs
     i64 n_graphs = 0;
+    // exact sums of H per graph (mass balance): limb slots and one double per graph
+    u64 *partH = nullptr;
+    double *hsum = nullptr;
     int rb = 0;
 };
 
@@ -143,6 +146,9 @@ int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevC
 // row blocks of OUT) that also sums the residual; additions in lane order, not row order.
 int launch_adj_sweep_fast(const DevGraph &g, const RowBlocks &rb_out, double *F, double *H, double *snap, DevCtl *ctl,
                           const SweepParams &p, hipStream_t st, u64 *partR, u64 *partC, i64 *nR, i64 *nC);
+// exact sum of H per graph of a union (else one sum) on 2^-K into out[0 .. n_graphs);
+// part: max(nranges, PART_MIN) * PSR words of scratch
+int launch_sum_history(const DevGraph &g, SolveState &s, int K, u64 *part, double *out, hipStream_t st);
 int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR);
 int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
                      hipStream_t st);

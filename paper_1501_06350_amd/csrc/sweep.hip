@@ -351,11 +351,11 @@ struct Bld2Args {
     const GraphCtl *gctl;
 };
 
-// LDS layout of k_bld2_sweep (bytes): F[B], dH[B] (fluid type), deg[B], off[B+1] (u32),
-// padding to 8, then per wave 64 x (q double, start u32), per wave a bitmap of
+// LDS layout of k_bld2_sweep (bytes): F[B] (fluid type), dH[B] (double), deg[B], off[B+1]
+// (u32), padding to 8, then per wave 64 x (q double, start u32), per wave a bitmap of
 // BLD2_SLOTS bits, then the targets.
 __host__ __device__ inline size_t bld2_scratch_offset(int B, int tsize) {
-    return ((size_t)2 * B * tsize + (size_t)4 * (2 * B + 1) + 7) & ~(size_t)7;
+    return ((size_t)B * tsize + (size_t)8 * B + (size_t)4 * (2 * B + 1) + 7) & ~(size_t)7;
 }
 
 // edge slots one wave lists before it pushes them (a multiple of 4 x 64)
@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     const int nthr = blockDim.x, nw = nthr >> 6;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
     T *Fl = reinterpret_cast<T *>(smem);
-    T *Dl = Fl + B;
+    double *Dl = reinterpret_cast<double *>(Fl + B);  // history increments, double for every fluid type
     unsigned *Deg = reinterpret_cast<unsigned *>(Dl + B);
     unsigned *Off = Deg + B;  // B + 1 entries
     double *sc_q_all = reinterpret_cast<double *>(smem + bld2_scratch_offset(B, (int)sizeof(T)));
@@ -485,7 +485,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             const int i = i0 + u * nthr;
             if (i < cnt) {
                 Fl[i] = fv[u];
-                Dl[i] = (T)0;
+                Dl[i] = 0.0;
                 Deg[i] = dv[u];
             }
         }
@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             unsigned st = 0;
             double q = 0.0;
             if (f != 0.0) {
-                atomicAdd(&Dl[i], (T)f);
+                atomicAdd(&Dl[i], f);
                 if (deg == 0) {
                     Ld += fabs(f);
                 } else {
@@ -676,7 +676,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int i = min(i0 + u * nthr, cnt - 1);
-            dh[u] = (double)Dl[i];
+            dh[u] = Dl[i];
             const unsigned df = Deg[i];
             rm[u] = (df & 0x80000000u) != 0;
             sv[u] = (dh[u] != 0.0 && (df & 0x80000000u))
@@ -1080,6 +1080,37 @@ int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipS
                                                  s.gctl, g.rb, skip_frozen);
     DI_LAUNCH_CHECK();
     s.nR = grid;
+    return DI_OK;
+}
+
+// Exact sum of the history per graph (one graph: one sum), for the mass balance
+// sum F + (1-d) sum H + d l = (1-d) sum Z that equation HnFn implies (the columns of P
+// sum to 1 except at dangling nodes, Section 2.1).  k_reduce_F leaves per-workgroup limb
+// slots (one per range in a union of graphs); one workgroup per graph adds its slots.
+__global__ void __launch_bounds__(256) k_sum_slots(const u64 *__restrict__ part, i64 nslots,
+                                                   const GraphInfo *__restrict__ gi, int K, double *out) {
+    __shared__ u64 red[4 * 4];
+    __shared__ u64 tot[4];
+    i64 b = 0, e = nslots;
+    if (gi) {
+        b = gi[blockIdx.x].rbeg;
+        e = gi[blockIdx.x].rend;
+    }
+    u64 v[4] = {0, 0, 0, 0};
+    for (i64 q = b + threadIdx.x; q < e; q += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += part[q * PSR + k];
+    block_store_partials<4>(v, red, tot);
+    if (threadIdx.x == 0) out[blockIdx.x] = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], K);
+}
+
+int launch_sum_history(const DevGraph &g, SolveState &s, int K, u64 *part, double *out, hipStream_t st) {
+    const unsigned grid = s.range_graph ? (unsigned)g.nranges : grid_for(g.n, 256, REDUCE_GRID);
+    k_reduce_F<double><<<grid, 256, 0, st>>>(s.H, g.n, K, s.ctl, part, s.range_graph, s.gctl, g.rb, 0);
+    DI_LAUNCH_CHECK();
+    const unsigned G = s.range_graph ? (unsigned)s.n_graphs : 1u;
+    k_sum_slots<<<G, 256, 0, st>>>(part, grid, s.range_graph ? s.ginfo : nullptr, K, out);
+    DI_LAUNCH_CHECK();
     return DI_OK;
 }
 

@@ -98,8 +98,13 @@ def test_tile_fast_certificates(gpu, case):
         Xn = s.read(gpu.X_NORM)
         L = s.read(gpu.LEAKS)
         done = s.read(gpu.DONE_SWEEPS)
+        MD = s.read(gpu.MASS_DEFECTS)
     assert (done >= 1).all() and done.max() == st["sweeps"]
+    assert len(MD) == k and st["mass_defect"] == MD[np.argmax(np.abs(MD))]
     for c in range(0, k, 9 if g.n > 2000 else 1):
+        md = O.mass_defect(og, D, Z[:, c], H[c], F[c], L[c])
+        slack = 1e-7 * R[c] if fp32 else 0.0
+        assert abs(MD[c]) <= slack + 1e-13 and abs(MD[c] - md) <= slack + 1e-14, (c, MD[c], md)
         x = exact(og, Z[:, c])
         assert R[c] / (1 - D) <= tol
         assert np.abs(H[c] - x).sum() <= R[c] / (1 - D) * (1 + 1e-7) + 1e-12, c
@@ -271,12 +276,17 @@ def test_union_fast_certificates(gpu, fp32):
         Xn = s.read(gpu.X_NORM)
         L = s.read(gpu.LEAKS)
         done = s.read(gpu.DONE_SWEEPS)
+        MD = s.read(gpu.MASS_DEFECTS)
     assert (done >= 0).all()
+    assert len(MD) == len(graphs) and st["mass_defect"] == MD[np.argmax(np.abs(MD))]
     for q, gq in enumerate(graphs):
         og = O.OGraph.of(gq)
         Zq = np.full(gq.n, 1.0 / gq.n)
         x = exact(og, Zq)
         sl = slice(gp[q], gp[q + 1])
+        md = O.mass_defect(og, D, Zq, H[sl], F[sl], L[q])
+        slack = 1e-7 * R[q] if fp32 else 0.0
+        assert abs(MD[q]) <= slack + 1e-13 and abs(MD[q] - md) <= slack + 1e-14, (q, MD[q], md)
         assert R[q] / (1 - D) <= tol
         assert np.abs(H[sl] - x).sum() <= R[q] / (1 - D) * (1 + 1e-7) + 1e-12, q
         d_inv = O.invariant_residual_l1(og, D, O.initial_fluid(D, Zq, False), H[sl], F[sl])

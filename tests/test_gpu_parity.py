@@ -135,10 +135,13 @@ def test_block_local_solve(gpu, oracle_graphs, name, fp32, rb):
         # certificate (Theorem 1); with float fluid the library recomputes F = F_0 + dPH - H
         # in double before it stops, so only the rounding of that F to float (2^-24) remains
         assert np.abs(H - x).sum() <= st["bound"] * (1 + 1e-7) + 1e-14
-        # mass balance: sum F + (1-d) sum H + d l = (1-d) sum Z
+        # mass balance: sum F + (1-d) sum H + d l = (1-d) sum Z, on the host and as the
+        # library reports it (exact sums on the device)
         l = s.read(gpu.LEAKS)[0]
-        defect = F.sum() + (1 - D) * H.sum() + D * l - (1 - D) * Z.sum()
+        defect = O.mass_defect(og, D, Z, H, F, l)
         assert abs(defect) <= (1e-6 if fp32 else 1e-13)
+        assert abs(st["mass_defect"] - defect) <= (1e-7 * st["residual"] if fp32 else 0) + 1e-14
+        assert s.read(gpu.MASS_DEFECTS)[0] == st["mass_defect"]
         # invariant H + F = F_0 + d P H (equation HnFn) with the exact F_0 = (1-d) Z, P
         # applied by the oracle; with float fluid its L1 defect is the rounding of the
         # recomputed fluid to float
@@ -163,6 +166,37 @@ def test_power_iteration(gpu, oracle_graphs, name, fp32):
         assert np.abs(xg - xo).sum() <= rel * np.abs(xo).sum()
         if not fp32:  # same iteration count up to a stop decision at the rounding boundary
             assert abs(st["sweeps"] - k) <= 1
+
+
+@pytest.mark.parametrize("kw", [{"deterministic": True}, {"range_cut": -1}, {}])
+def test_set_z_back_to_uniform(gpu, kw):
+    """A context built with an explicit Z and then given Z = NULL solves the uniform
+    problem: power iteration and D-Iteration equal a fresh uniform-Z context's results
+    (bit for bit in deterministic mode)."""
+    g = GRAPHS["web20k"]
+    Zr = np.random.default_rng(4).random(g.n)
+    say("set_z(None)", kw)
+    with gpu.from_graph(g, d=D, **kw) as fresh:
+        st0 = fresh.diffuse(1e-11)
+        H0 = fresh.read(gpu.H)
+        p0 = fresh.power(1e-11)
+        X0 = fresh.read(gpu.X_PI)
+    with gpu.from_graph(g, d=D, Z=Zr, **kw) as s:
+        s.diffuse(1e-11)
+        s.power(1e-11)
+        s.set_z(None)
+        st1 = s.diffuse(1e-11)
+        H1 = s.read(gpu.H)
+        p1 = s.power(1e-11)
+        X1 = s.read(gpu.X_PI)
+    assert p1["converged"] and p1["sweeps"] == p0["sweeps"] > 1
+    np.testing.assert_array_equal(X1, X0)
+    if kw.get("deterministic"):
+        assert st1["sweeps"] == st0["sweeps"]
+        np.testing.assert_array_equal(H1, H0)
+    else:
+        x = np.abs(H0).sum()
+        assert np.abs(H1 - H0).sum() <= st0["bound"] + st1["bound"] + 1e-15 * x
 
 
 def test_deterministic_theta0_matches_power_iterates(gpu, oracle_graphs):

@@ -46,6 +46,11 @@ def test_webgen_1m_against_oracle(gpu):
             say("DI fp32=%d: %d sweeps, bound %.3e, |H - x_ref|_1 = %.3e" % (fp32, st["sweeps"], st["bound"], err))
             assert err <= st["bound"] * (1 + 1e-6) + xb + 1e-15 * xn
             assert err <= rel * xn
+            # mass balance reported by the library against the oracle's sums of the result
+            md = O.mass_defect(og, D, Z, H, s.read(gpu.F), s.read(gpu.LEAKS)[0])
+            say("mass defect: library %.3e, oracle %.3e" % (st["mass_defect"], md))
+            assert abs(st["mass_defect"]) <= (1e-7 * st["residual"] if fp32 else 0) + 1e-13 * Z.sum()
+            assert abs(st["mass_defect"] - md) <= (1e-7 * st["residual"] if fp32 else 0) + 1e-13 * Z.sum()
             p = s.power(tol)
             xp = s.read(gpu.X_PI)
             errp = float(np.abs(xp - x).sum())
@@ -75,7 +80,14 @@ def test_headline_50m_certificate(gpu, web50m, fp32):
         assert st["converged"] and st["bound"] <= 1e-8
         H = s.read(gpu.H)
         Fg = s.read(gpu.F)
+        lg = s.read(gpu.LEAKS)[0]
     say("DI: %d sweeps, bound %.3e" % (st["sweeps"], st["bound"]))
+    # mass balance at the full size: the library's exact device sums against the oracle's
+    md = O.mass_defect(og, D, Z, H, Fg, lg)
+    say("mass defect: library %.3e, oracle %.3e" % (st["mass_defect"], md))
+    slack = 1e-7 * st["residual"] if fp32 else 0.0
+    assert abs(st["mass_defect"]) <= slack + 1e-13 * Z.sum()
+    assert abs(st["mass_defect"] - md) <= slack + 1e-13 * Z.sum()
     assert np.all(H >= 0)
     # every row: the certificate from the oracle's own residual
     R = exact_residual_l1(og, F0, H)
@@ -114,8 +126,15 @@ def test_tile_k64_columns_certified_by_oracle(gpu):
         st = s.diffuse(1e-8)
         assert st["converged"]
         H = s.read(gpu.H)
+        F = s.read(gpu.F)
+        leaks, res, mds = s.read(gpu.LEAKS), s.read(gpu.RESIDUALS), s.read(gpu.MASS_DEFECTS)
     og = O.OGraph.of(g)
+    assert st["mass_defect"] == mds[np.argmax(np.abs(mds))]
     for c in (0, 9, 31, 63):
         R = exact_residual_l1(og, (1 - D) * Z[:, c], H[c])
         say("column %d: oracle residual bound %.4e" % (c, R / (1 - D)))
         assert R / (1 - D) <= 1e-8 * (1 + 1e-6)
+        md = O.mass_defect(og, D, Z[:, c], H[c], F[c], leaks[c])
+        say("column %d: mass defect library %.3e, oracle %.3e" % (c, mds[c], md))
+        assert abs(mds[c]) <= 1e-7 * res[c] + 1e-13
+        assert abs(mds[c] - md) <= 1e-7 * res[c] + 1e-13

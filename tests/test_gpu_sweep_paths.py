@@ -2,8 +2,9 @@
 
 The graph is built so that every path of the local rounds runs:
 - a 64-node chunk whose nodes carry 300 local edges each (19,200 edge slots, more than one
-  push list holds) and a single node with 1,500 local edges: the per-chunk pass with a
-  binary search over the chunk's nodes (one node or many);
+  push list holds) and a single node with 1,500 local edges: the oversized-chunk path,
+  where the chunk's nodes push one at a time with the whole wave striding over each
+  node's edges (one node or many);
 - chunks of 64 nodes with 12 edges each (768 slots): lists that fill on edge slots;
 - chunks of 64 nodes with one edge each: lists that fill on nodes;
 - dangling nodes and a sparse background with 80% short edges.
