@@ -50,6 +50,8 @@ def _load():
     lib.or_fixed_scale.restype = ci
     lib.or_fixed_sum_abs.argtypes = [i64, vp, ci]
     lib.or_fixed_sum_abs.restype = dbl
+    lib.or_fixed_sum_signed.argtypes = [i64, vp, ci, vp]
+    lib.or_fixed_sum_signed.restype = dbl
     lib.or_fixed_value.argtypes = [vp, ci]
     lib.or_fixed_value.restype = dbl
     lib.or_di_sequential.argtypes = [i64, vp, vp, vp, vp, dbl, vp, vp, vp, ci, i64, dbl, vp]
@@ -161,6 +163,23 @@ def fixed_sum_abs(v: np.ndarray, K: int) -> float:
     return float(_load().or_fixed_sum_abs(len(v), _p(v), K))
 
 
+def fixed_sum_signed(v: np.ndarray, K: int):
+    """Exact signed sum of v on 2^-K: (value rounded once to double, [low, high] 64-bit
+    words of the two's-complement 128-bit integer)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(2, dtype=np.uint64)
+    val = float(_load().or_fixed_sum_signed(len(v), _p(v), K, _p(out)))
+    return val, out
+
+
+def update_fluid(og_old: "OGraph", og_new: "OGraph", d: float, H: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """Theorem 4 (Section 3.5): after diffusions on P reached (H, F), D-Iteration on P'
+    continues from H'_0 = H and F'_0 = F + d (P' - P) H.  (P' - P) H is evaluated as
+    P' H - P H, each product a left fold over its IN rows (unchanged rows cancel exactly)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    return np.asarray(F, dtype=np.float64) + d * (og_new.P_times(H) - og_old.P_times(H))
+
+
 def initial_fluid(d: float, Z: np.ndarray, fluid_fp32: bool = False) -> np.ndarray:
     """F_0 = (1-d) Z (Section 3.1), rounded to float when the fluid is stored in float."""
     F = (1.0 - d) * np.asarray(Z, dtype=np.float64)
@@ -197,6 +216,15 @@ class SequentialDI:
     def residual(self) -> float:
         return float(np.abs(self.F).sum())
 
+    def update(self, og_new: "OGraph") -> None:
+        """Switch to the matrix P' of og_new (same nodes) by Theorem 4: keep H, set
+        F = F + d (P' - P) H (signed), and count as leaked the history at the nodes
+        dangling in P' (the fluid those diffusions would have lost under P')."""
+        assert og_new.n == self.og.n
+        self.F = update_fluid(self.og, og_new, self.d, self.H, self.F)
+        self.og = og_new
+        self.l[0] = float(self.H[og_new.dangling].sum())
+
 
 # --------------------------------------------------------------------------
 # Synchronous-sweep D-Iteration (the GPU's deterministic sweep)
@@ -205,6 +233,7 @@ class SyncDI:
     def __init__(self, og: OGraph, d: float, Z: np.ndarray, theta: float = 1.0, fluid_fp32: bool = False):
         self.og, self.d, self.theta, self.fp32 = og, float(d), float(theta), bool(fluid_fp32)
         self.F = initial_fluid(d, Z, fluid_fp32)
+        self.F_init = self.F.copy()
         self.K = fixed_scale(self.F)
         self.H = np.zeros(og.n)
         self.l_fixed = np.zeros(2, dtype=np.uint64)
@@ -231,6 +260,23 @@ class SyncDI:
         if record_frontier and t > 0:
             self.last_frontier = fr[: int(flen[0])].copy()
         return int(t)
+
+    def update(self, og_new: "OGraph") -> None:
+        """Switch to the matrix P' of og_new (same nodes) by Theorem 4 (Section 3.5): keep H,
+        set F = F + d (P' - P) H (signed; rounded once to float in the float-fluid mode),
+        choose the fixed-point scale for the new fluid, and set the leak to the exact sum of
+        H over the nodes dangling in P' (those diffusions lose their fluid under P')."""
+        assert og_new.n == self.og.n
+        F = update_fluid(self.og, og_new, self.d, self.H, self.F)
+        if self.fp32:
+            F = F.astype(np.float32).astype(np.float64)
+        self.F = F
+        self.og = og_new
+        # the scale covers the new fluid and, as before, the starting fluid (which bounds
+        # the leak: n max F_0 >= (1-d) |Z|_1 >= (1-d) l)
+        self.K = fixed_scale(np.maximum(np.abs(F), np.abs(self.F_init)))
+        self.l_fixed = fixed_sum_signed(self.H[og_new.dangling], self.K)[1]
+        self.converged = False
 
     @property
     def R(self) -> float:

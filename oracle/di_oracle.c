@@ -103,6 +103,31 @@ static inline u128 fixed_of(double v, int K) {
 
 static inline double fixed_to_double(u128 acc, int K) { return ldexp((double)acc, -K); }
 
+/* A signed fixed-point accumulator holds its value modulo 2^128 (two's complement): a
+ * negative v adds 2^128 - floor(|v| 2^K).  Sums stay below 2^118 in magnitude (see
+ * or_fixed_scale), so the top bit tells the sign. */
+static inline u128 fixed_of_signed(double v, int K) {
+    u128 q = fixed_of(v, K);
+    return v < 0.0 ? (u128)0 - q : q;
+}
+
+static inline double fixed_to_double_signed(u128 acc, int K) {
+    if (acc >> 127) return -ldexp((double)((u128)0 - acc), -K);
+    return ldexp((double)acc, -K);
+}
+
+/* Exact signed sum of v on 2^-K as a two's-complement u128 (out[0] low, out[1] high
+ * 64 bits); returns the value rounded once to double. */
+double or_fixed_sum_signed(int64_t n, const double *v, int K, uint64_t *out) {
+    u128 acc = 0;
+    for (int64_t i = 0; i < n; ++i) acc += fixed_of_signed(v[i], K);
+    if (out) {
+        out[0] = (uint64_t)acc;
+        out[1] = (uint64_t)(acc >> 64);
+    }
+    return fixed_to_double_signed(acc, K);
+}
+
 double or_fixed_sum_abs(int64_t n, const double *v, int K) {
     u128 acc = 0;
     for (int64_t i = 0; i < n; ++i) acc += fixed_of(v[i], K);
@@ -138,7 +163,8 @@ static double plain_l1(int64_t n, const double *F) {
  * Run up to max_steps elementary diffusions.
  *   sched 0 (DI-cyc, Section 3.4): round robin over 0..n-1.
  *   sched 1 (DI-argmax, Section 3.4): round robin, but skip nodes whose fluid is
- *           below the average fluid |F|_1 / n of the whole graph.
+ *           below the average fluid |F|_1 / n of the whole graph (compared in
+ *           magnitude: after a graph update, Theorem 4, fluid may be negative).
  * *pos is the round-robin pointer (next candidate), kept across calls.
  * Stops early when |F|_1 / (1-d) <= tol (tol <= 0 disables).  Returns steps done.
  */
@@ -156,12 +182,12 @@ int64_t or_di_sequential(int64_t n, const int64_t *out_ptr, const int32_t *out_i
              * because the maximum is at least the average */
             double avg = R / (double)n;
             int64_t tries = 0;
-            while (F[i] < avg && tries < n) { i = (i + 1) % n; ++tries; }
+            while (fabs(F[i]) < avg && tries < n) { i = (i + 1) % n; ++tries; }
             if (tries == n) { /* only possible through rounding in R: recompute */
                 R = plain_l1(n, F);
                 avg = R / (double)n;
                 tries = 0;
-                while (F[i] < avg && tries < n) { i = (i + 1) % n; ++tries; }
+                while (fabs(F[i]) < avg && tries < n) { i = (i + 1) % n; ++tries; }
             }
         }
         diffuse_one(i, out_ptr, out_idx, w, inv_s, d, F, H, l);
@@ -188,7 +214,8 @@ int64_t or_di_sequential(int64_t n, const int64_t *out_ptr, const int32_t *out_i
  *   F_j += sum over IN row j, ascending source i in A_t, of (d * f_i) * inv_s_i (* w_e)
  *          as a left fold starting from F_j, in double; with fluid_fp32 the fold's
  *          result is rounded to float once.
- *   l    : dangling sources in A_t add floor(f_i * 2^K) to the integer l_fixed.
+ *   l    : dangling sources in A_t add floor(|f_i| * 2^K), with the sign of f_i, to the
+ *          integer l_fixed (two's complement; fluid is signed after a graph update).
  * trace (optional, 3 doubles per sweep): R_t, |A_t|, edges pushed.
  * frontier (optional): indices of the last sweep's A_t, ascending; *frontier_len set.
  * Returns the number of sweeps that pushed; *converged = 1 if the stop test passed.
@@ -222,7 +249,7 @@ int64_t or_di_sync(int64_t n, const int64_t *out_ptr, const int64_t *in_ptr, con
             double f = F[i];
             H[i] += f;
             F[i] = 0.0;
-            if (out_ptr[i + 1] == out_ptr[i]) lacc += fixed_of(f, K);
+            if (out_ptr[i + 1] == out_ptr[i]) lacc += fixed_of_signed(f, K);
             else q[i] = (d * f) * inv_s[i];
             edges += out_ptr[i + 1] - out_ptr[i];
         }
@@ -252,7 +279,7 @@ int64_t or_di_sync(int64_t n, const int64_t *out_ptr, const int64_t *in_ptr, con
 
 double or_fixed_value(const uint64_t *l_fixed, int K) {
     u128 a = ((u128)l_fixed[1] << 64) | (u128)l_fixed[0];
-    return fixed_to_double(a, K);
+    return fixed_to_double_signed(a, K);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -435,3 +435,128 @@ def test_gradients_vs_finite_differences(weighted):
         Zm[i] -= h
         fd = (loss(g.w, Zp) - loss(g.w, Zm)) / (2 * h)
         assert abs(fd - dZ[i]) <= 1e-7 + 1e-6 * abs(dZ[i])
+
+
+# --------------------------------------------------------------------------
+# Graph update (Section 3.5, Theorem 4)
+# --------------------------------------------------------------------------
+def rewired(g, seed, frac=0.08, weighted=False):
+    """g with a share of its edges moved to new targets, some edges dropped (sources may
+    become dangling) and edges added at dangling nodes: same nodes, another matrix P'."""
+    rng = np.random.default_rng(seed)
+    src = np.repeat(np.arange(g.n), np.diff(g.out_ptr))
+    dst = g.out_idx.astype(np.int64).copy()
+    w = None if g.w is None else g.w.copy()
+    move = rng.random(len(dst)) < frac
+    dst[move] = rng.integers(0, g.n, size=int(move.sum()))
+    keep = rng.random(len(dst)) >= frac / 2
+    src, dst = src[keep], dst[keep]
+    w = None if w is None else w[keep]
+    dang = np.flatnonzero(np.diff(g.out_ptr) == 0)
+    new_src = rng.choice(dang, size=max(1, len(dang) // 3), replace=False) if len(dang) else np.zeros(0, int)
+    src = np.concatenate([src, new_src])
+    dst = np.concatenate([dst, rng.integers(0, g.n, size=len(new_src))])
+    if w is not None:
+        w = np.concatenate([w, rng.lognormal(0, 1, size=len(new_src)).astype(np.float32)])
+    return W.from_edges(g.n, src, dst, w, g.name + "'")
+
+
+def test_update_hand_fixture():
+    case = json.load(open(GOLDEN))["updates"][0]
+    fr = lambda a: np.array([float(Fraction(v)) for v in a])
+    d = float(Fraction(case["d"]))
+    Z = fr(case["Z"])
+
+    def graph(key):
+        e = case[key]
+        return O.OGraph.of(W.from_edges(case["n"], [a for a, _, _ in e], [b for _, b, _ in e], None, key))
+
+    a, b = graph("edges_before"), graph("edges_after")
+    s = O.SequentialDI(a, d, Z, "cyc")
+    s.run(case["steps_before"])
+    np.testing.assert_allclose(s.H, fr(case["H_before"]), rtol=0, atol=1e-16)
+    np.testing.assert_allclose(s.F, fr(case["F_before"]), rtol=0, atol=1e-16)
+    s.update(b)
+    np.testing.assert_allclose(s.F, fr(case["F_after"]), rtol=0, atol=1e-16)
+    assert s.F.min() < 0  # the update brings negative fluid (remark after Theorem 4)
+    s.run(10 ** 5, tol=1e-15)
+    np.testing.assert_allclose(s.H, fr(case["x_after"]), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(O.dense_solve(b, d, Z), fr(case["x_after"]), rtol=0, atol=1e-15)
+    # the synchronous sweep, updated at another point, reaches the same fixed point
+    y = O.SyncDI(a, d, Z)
+    y.run(1e-300, max_sweeps=3)
+    y.update(b)
+    y.run(1e-15)
+    assert y.converged
+    np.testing.assert_allclose(y.H, fr(case["x_after"]), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("sched", ["cyc", "argmax", "sync"])
+def test_update_invariants_and_limit(weighted, sched):
+    """After the update: equation HnFn holds for P' (with the original F_0), |F|_1 never
+    grows, Theorem 1's certificate holds for the signed fluid, the mass balance holds with
+    the leak reset to the history at P'-dangling nodes, and H reaches the dense solution of
+    x' = d P' x' + (1-d) Z."""
+    g = random_graph(60, 21, weighted)
+    g2 = rewired(g, 5, weighted=weighted)
+    oa, ob = O.OGraph.of(g), O.OGraph.of(g2)
+    assert ob.dangling.sum() != oa.dangling.sum() or (ob.dangling != oa.dangling).any()
+    P2 = P_numpy(g2)
+    Z = np.random.default_rng(4).random(g.n)
+    Z /= Z.sum()
+    x2 = O.dense_solve(ob, D, Z)
+    F0 = O.initial_fluid(D, Z)
+    dang2 = np.diff(g2.out_ptr) == 0
+    if sched == "sync":
+        s = O.SyncDI(oa, D, Z)
+        s.run(1e-300, max_sweeps=4)
+    else:
+        s = O.SequentialDI(oa, D, Z, sched)
+        s.run(150)
+    s.update(ob)
+    assert s.F.min() < 0
+    R_prev = np.inf
+    for _ in range(400):
+        assert np.abs(s.H + s.F - F0 - D * (P2 @ s.H)).max() < 1e-15
+        R = np.abs(s.F).sum()
+        assert R <= R_prev * (1 + 1e-15) + 1e-17
+        assert np.abs(x2 - s.H).sum() <= R / (1 - D) + 1e-15
+        l = s.l if sched == "sync" else s.l[0]
+        assert abs(l - s.H[dang2].sum()) < 1e-15
+        assert abs(s.F.sum() + (1 - D) * s.H.sum() + D * l - (1 - D) * Z.sum()) < 1e-15
+        R_prev = R
+        if sched == "sync":
+            s.run(1e-14, max_sweeps=1)
+            if s.converged:
+                break
+        else:
+            s.run(30)
+    if sched != "sync":
+        s.run(10 ** 6, tol=1e-14)
+    assert np.abs(x2 - s.H).sum() <= 1e-13
+
+
+def test_update_to_the_same_graph_changes_nothing():
+    g = random_graph(80, 3, weighted=True)
+    og, og2 = O.OGraph.of(g), O.OGraph.of(g)
+    y = O.SyncDI(og, D, O.uniform_Z(g.n))
+    y.run(1e-300, max_sweeps=5)
+    F, H = y.F.copy(), y.H.copy()
+    y.update(og2)
+    np.testing.assert_array_equal(y.F, F)
+    np.testing.assert_array_equal(y.H, H)
+
+
+def test_update_pin_detects_a_wrong_sign():
+    """Injecting d (P - P') H instead of d (P' - P) H (a plausible slip) misses x'."""
+    g = random_graph(60, 21)
+    og, og2 = O.OGraph.of(g), O.OGraph.of(rewired(g, 5))
+    Z = O.uniform_Z(g.n)
+    x2 = O.dense_solve(og2, D, Z)
+    s = O.SequentialDI(og, D, Z, "cyc")
+    s.run(150)
+    s.F = O.update_fluid(og2, og, D, s.H, s.F)  # operands swapped
+    s.og = og2
+    s.run(10 ** 6, tol=1e-14)
+    assert np.abs(x2 - s.H).sum() > 1e-3
