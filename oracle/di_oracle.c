@@ -138,62 +138,56 @@ double or_fixed_sum_abs(int64_t n, const double *v, int K) {
 /* Sequential D-Iteration (Section 3.1) with the Section 3.4 schedulers        */
 /* ------------------------------------------------------------------------- */
 
-/* One elementary diffusion of node i (equation defF): returns the fluid moved. */
-static double diffuse_one(int64_t i, const int64_t *out_ptr, const int32_t *out_idx, const float *w,
-                          const double *inv_s, double d, double *F, double *H, double *l) {
-    double f = F[i];
-    H[i] += f;
-    F[i] = 0.0; /* the local fluid is cleared, then any self-loop share comes back */
-    if (out_ptr[i + 1] == out_ptr[i]) {
-        *l += f; /* fluid leaving through a dangling node (Section 3.3) */
-        return f;
-    }
-    for (int64_t e = out_ptr[i]; e < out_ptr[i + 1]; ++e)
-        F[out_idx[e]] += d * f * p_entry(w, e, inv_s[i]);
-    return f;
-}
-
-static double plain_l1(int64_t n, const double *F) {
-    double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += fabs(F[i]);
-    return s;
-}
-
 /*
  * Run up to max_steps elementary diffusions.
  *   sched 0 (DI-cyc, Section 3.4): round robin over 0..n-1.
  *   sched 1 (DI-argmax, Section 3.4): round robin, but skip nodes whose fluid is
  *           below the average fluid |F|_1 / n of the whole graph (compared in
  *           magnitude: after a graph update, Theorem 4, fluid may be negative).
- * *pos is the round-robin pointer (next candidate), kept across calls.
- * Stops early when |F|_1 / (1-d) <= tol (tol <= 0 disables).  Returns steps done.
+ * |F|_1 is the fixed-point sum (K from or_fixed_scale of the F given to the call), kept
+ * exact as F changes: each changed entry removes its old term and adds its new one, so
+ * a step costs its out-degree, not n.  *pos is the round-robin pointer (next candidate),
+ * kept across calls.  Stops early when |F|_1 / (1-d) <= tol (tol <= 0 disables).
+ * Returns steps done.
  */
 int64_t or_di_sequential(int64_t n, const int64_t *out_ptr, const int32_t *out_idx, const float *w,
                          const double *inv_s, double d, double *F, double *H, double *l, int sched,
                          int64_t max_steps, double tol, int64_t *pos) {
     int64_t steps = 0;
     int64_t p = *pos;
-    double R = plain_l1(n, F);
+    const int K = or_fixed_scale(n, F);
+    u128 Rf = 0;
+    for (int64_t i = 0; i < n; ++i) Rf += fixed_of(F[i], K);
     while (steps < max_steps) {
+        const double R = fixed_to_double(Rf, K);
         if (tol > 0.0 && R / (1.0 - d) <= tol) break;
         int64_t i = p;
         if (sched == 1) {
-            /* first node at or after p with F >= average; a full cycle always finds one
-             * because the maximum is at least the average */
-            double avg = R / (double)n;
+            /* first node at or after p with |F| >= average; a full cycle always finds one
+             * because the largest |F_i| is at least the average */
+            const double avg = R / (double)n;
             int64_t tries = 0;
             while (fabs(F[i]) < avg && tries < n) { i = (i + 1) % n; ++tries; }
-            if (tries == n) { /* only possible through rounding in R: recompute */
-                R = plain_l1(n, F);
-                avg = R / (double)n;
-                tries = 0;
-                while (fabs(F[i]) < avg && tries < n) { i = (i + 1) % n; ++tries; }
+        }
+        /* one elementary diffusion of node i (equation defF), the residual's terms updated:
+         * the local fluid moves to H and is cleared, then d f P e_i goes out (any
+         * self-loop share comes back) */
+        Rf -= fixed_of(F[i], K);
+        const double f = F[i];
+        H[i] += f;
+        F[i] = 0.0;
+        if (out_ptr[i + 1] == out_ptr[i]) {
+            *l += f; /* fluid leaving through a dangling node (Section 3.3) */
+        } else {
+            for (int64_t e = out_ptr[i]; e < out_ptr[i + 1]; ++e) {
+                const int32_t t = out_idx[e];
+                Rf -= fixed_of(F[t], K);
+                F[t] += d * f * p_entry(w, e, inv_s[i]);
+                Rf += fixed_of(F[t], K);
             }
         }
-        diffuse_one(i, out_ptr, out_idx, w, inv_s, d, F, H, l);
         p = (i + 1) % n;
         ++steps;
-        if (sched == 1 || tol > 0.0) R = plain_l1(n, F);
     }
     *pos = p;
     return steps;

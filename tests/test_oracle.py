@@ -287,6 +287,29 @@ def test_sequential_invariants(sched, weighted):
         prevH, prevR = s.H.copy(), R
 
 
+@pytest.mark.parametrize("sched", ["cyc", "argmax"])
+def test_sequential_stop_follows_the_exact_residual(sched):
+    """The sequential solver keeps |F|_1 as a running fixed-point sum; it must stop at the
+    first step whose full re-sum of |F| meets the tolerance (graph with self-loops, repeated
+    edges, weights and dangling nodes)."""
+    g0 = random_graph(50, 31, weighted=True)
+    src = np.concatenate([np.repeat(np.arange(g0.n), np.diff(g0.out_ptr)), [3, 3, 7, 11]])
+    dst = np.concatenate([g0.out_idx, [3, 3, 7, 11]])  # self-loops, one of them repeated
+    w = np.concatenate([g0.w, np.array([0.5, 2.0, 1.0, 3.0], dtype=np.float32)])
+    g = W.from_edges(g0.n, src, dst, w, "loops")
+    og = O.OGraph.of(g)
+    Z = np.random.default_rng(6).random(g.n)
+    K = O.fixed_scale(O.initial_fluid(D, Z))
+    for tol in (1e-3, 1e-6, 1e-9):
+        s = O.SequentialDI(og, D, Z, sched)
+        k = s.run(10 ** 6, tol=tol)
+        assert 0 < k < 10 ** 6
+        assert O.fixed_sum_abs(s.F, K) / (1 - D) <= tol
+        t = O.SequentialDI(og, D, Z, sched)
+        t.run(k - 1)
+        assert O.fixed_sum_abs(t.F, K) / (1 - D) > tol
+
+
 def test_bound_is_equality_without_dangling_nodes():
     g = random_graph(25, 4, weighted=True, p_dangling=0.0)
     og = O.OGraph.of(g)
