@@ -60,6 +60,8 @@ def _load():
     lib.or_di_sync.restype = i64
     lib.or_power.argtypes = [i64, vp, vp, vp, vp, dbl, vp, vp, dbl, i64, vp, vp]
     lib.or_power.restype = i64
+    lib.or_gauss_seidel.argtypes = [i64, vp, vp, vp, vp, dbl, vp, vp, i64]
+    lib.or_gauss_seidel.restype = None
     lib.or_adjoint_sync.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, ci, vp, vp, dbl, i64, vp]
     lib.or_adjoint_sync.restype = i64
     lib.or_edge_grad.argtypes = [i64, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
@@ -305,6 +307,16 @@ def power(og: OGraph, d: float, Z: np.ndarray, tol: float, max_iters: int = 1000
     if k < 0:
         raise MemoryError("or_power")
     return x, int(k), tr[:k].copy()
+
+
+def gauss_seidel(og: OGraph, d: float, Z: np.ndarray, x0, sweeps: int) -> np.ndarray:
+    """`sweeps` Gauss-Seidel rounds (Section 2.3) from x0: entries updated in place in
+    index order, so row i reads the new values of the rows before it."""
+    x = np.array(x0, dtype=np.float64)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    _load().or_gauss_seidel(og.n, _p(og.in_ptr), _p(og.in_idx), _p(og.in_w), _p(og.inv_s), float(d), _p(Z), _p(x),
+                            int(sweeps))
+    return x
 
 
 # --------------------------------------------------------------------------

@@ -316,6 +316,30 @@ int64_t or_power(int64_t n, const int64_t *in_ptr, const int32_t *in_idx, const 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Gauss-Seidel (Section 2.3), a comparison method for the convergence curves   */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * `sweeps` rounds of x(i) = d (sum_{j<i} P[i][j] x_new(j) + sum_{j>=i} P[i][j] x_old(j))
+ * + (1-d) Z(i) for i = 0 .. n-1: one vector updated in place in index order, so the
+ * entries below i are already the new ones.  Each row is a left fold over its IN row in
+ * source order.  x holds the start vector on entry.
+ */
+void or_gauss_seidel(int64_t n, const int64_t *in_ptr, const int32_t *in_idx, const float *in_w,
+                     const double *inv_s, double d, const double *Z, double *x, int64_t sweeps) {
+    for (int64_t k = 0; k < sweeps; ++k) {
+        for (int64_t i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int64_t p = in_ptr[i]; p < in_ptr[i + 1]; ++p) {
+                int32_t j = in_idx[p];
+                acc += (in_w ? (double)in_w[p] * inv_s[j] : inv_s[j]) * x[j];
+            }
+            x[i] = d * acc + (1.0 - d) * Z[i];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Adjoint: lambda = (I - d P^T)^{-1} g by diffusion on the transposed matrix   */
 /* ------------------------------------------------------------------------- */
 

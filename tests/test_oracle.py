@@ -365,6 +365,34 @@ def test_power_certificate():
         assert np.abs(x - xk1).sum() <= D * gap / (1 - D) + 1e-15
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gauss_seidel(weighted):
+    """Gauss-Seidel (Section 2.3): with every edge pointing to a higher index, P is strictly
+    lower triangular and one round is forward substitution, the exact solution; with every
+    edge pointing to a lower index no row reads a new value, so one round is one power
+    iteration; on a general graph the rounds converge to the dense solution."""
+    rng = np.random.default_rng(17)
+    n = 70
+    src = rng.integers(0, n, size=300)
+    dst = rng.integers(0, n, size=300)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    w = rng.lognormal(0, 1, size=len(src)).astype(np.float32) if weighted else None
+    Z = rng.random(n)
+    lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+    up = O.OGraph.of(W.from_edges(n, lo, hi, w))  # j -> i with j < i
+    x = O.dense_solve(up, D, Z)
+    np.testing.assert_allclose(O.gauss_seidel(up, D, Z, np.zeros(n), 1), x, rtol=1e-13, atol=1e-16)
+    down = O.OGraph.of(W.from_edges(n, hi, lo, w))  # j -> i with j > i
+    x0 = rng.random(n)
+    x1, _, _ = O.power(down, D, Z, tol=1e-300, max_iters=1, x0=x0)
+    np.testing.assert_allclose(O.gauss_seidel(down, D, Z, x0, 1), x1, rtol=1e-14, atol=1e-17)
+    og = O.OGraph.of(random_graph(120, 5, weighted))
+    Zg = O.uniform_Z(og.n)
+    xg = O.dense_solve(og, D, Zg)
+    assert np.abs(O.gauss_seidel(og, D, Zg, np.zeros(og.n), 300) - xg).sum() <= 1e-14
+
+
 def test_permutation_invariance():
     g = random_graph(80, 12, weighted=True)
     perm = np.random.default_rng(5).permutation(g.n)
