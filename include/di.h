@@ -215,6 +215,32 @@ int di_adjoint(di_ctx *ctx, const double *g, double tol_inf, double *dZ, double 
 /* Copy a result into dst (host if dst_on_device = 0, device otherwise). */
 int di_read(di_ctx *ctx, int what, void *dst, int dst_on_device);
 
+/*
+ * Graph update (Section 3.5, Theorem 4): replace the context's graph by g (same n, any
+ * edges and weights; host or device arrays, validated as in di_init) and keep the
+ * D-Iteration state, so that the next di_diffuse converges to the solution of
+ * x' = d P' x' + (1-d) Z:
+ *     H' = H,   F' = F + d (P' - P) H   (evaluated as P'H - PH; fluid may turn negative),
+ * and the leak restarts as the history at the nodes dangling in P' (Section 3.3).  The
+ * certificate |x' - H'|_1 <= |F'|_1 / (1-d) holds for signed fluid too (Theorem 1's proof
+ * only uses |P'|_1 <= 1).  Deterministic contexts evaluate P H as a left fold over each IN
+ * row in source order (bit-reproducible).  Z, d and the options are kept; the device graph,
+ * its layout and the power-iteration and adjoint state are rebuilt (the old graph is
+ * released; both are resident during the call).  Single right-hand side, single graph.
+ * Errors: DI_EINVAL (bad graph, other n, several columns or graphs), DI_ENOMEM, DI_EHIP;
+ * on error the context is unchanged.
+ */
+int di_update(di_ctx *ctx, const di_csr *g);
+
+/*
+ * Change the frontier scale theta (>= 0) and, when inner_rounds > 0, the block-local rounds
+ * per sweep (1..64) of a context; the graph and the D-Iteration state are kept, so the next
+ * di_diffuse continues with the new options (any schedule keeps equation HnFn).  For
+ * tuning and for schedules that change theta as the residual falls.  DI_EINVAL on bad
+ * values.
+ */
+int di_set_sweep(di_ctx *ctx, double theta, int inner_rounds);
+
 /* Back to F = (1-d) Z, H = 0, l = 0 (graph and PI state kept). */
 int di_reset(di_ctx *ctx);
 

@@ -25,8 +25,8 @@ INFO_N, INFO_M, INFO_K, INFO_M_LOCAL, INFO_RANGE_LOG2, INFO_INNER_ROUNDS, INFO_F
     INFO_DEVICE_BYTES, INFO_KERNEL_NS, INFO_KERNEL_LAUNCHES, INFO_LOCAL_PUSHES, INFO_REMOTE_UPDATES, INFO_M_REMOTE, \
     INFO_NRANGES, INFO_N_INTERNAL = range(16)
 
-EXPORTED = ["di_init", "di_diffuse", "di_power", "di_adjoint", "di_read", "di_reset", "di_set_z", "di_save",
-            "di_load", "di_info", "di_destroy", "di_last_error"]
+EXPORTED = ["di_init", "di_diffuse", "di_power", "di_adjoint", "di_read", "di_update",
+            "di_set_sweep", "di_reset", "di_set_z", "di_save", "di_load", "di_info", "di_destroy", "di_last_error"]
 
 
 class DIError(RuntimeError):
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     lib.di_power.argtypes = [vp, dbl, ctypes.POINTER(DiStats)]
     lib.di_adjoint.argtypes = [vp, vp, dbl, vp, vp, ci, ctypes.POINTER(DiStats)]
     lib.di_read.argtypes = [vp, ci, vp, ci]
+    lib.di_update.argtypes = [vp, ctypes.POINTER(DiCsr)]
+    lib.di_set_sweep.argtypes = [vp, dbl, ci]
     lib.di_reset.argtypes = [vp]
     lib.di_set_z.argtypes = [vp, vp]
     lib.di_save.argtypes = [vp, ctypes.c_char_p]
@@ -239,6 +241,26 @@ class Solver:
         if arr.size:
             _check(self._lib.di_read(self._ctx, what, ctypes.c_void_p(arr.ctypes.data), 0))
         return arr
+
+    def update(self, out_ptr, out_idx, w=None):
+        """Replace the graph (same n) and keep the D-Iteration state (Theorem 4)."""
+        p_ptr, k_ptr, dev0 = _ptr(out_ptr, np.int64)
+        p_idx, k_idx, dev1 = _ptr(out_idx, np.int32)
+        p_w, k_w, dev2 = _ptr(w, np.float32)
+        if len({dev0, dev1} | ({dev2} if w is not None else set())) != 1:
+            raise ValueError("graph arrays must all be on the host or all on the device")
+        m = int(k_idx.shape[0]) if k_idx is not None else 0
+        csr = DiCsr(self.n, m, p_ptr, p_idx, p_w, dev0)
+        _check(self._lib.di_update(self._ctx, ctypes.byref(csr)))
+        self.m = m
+        del k_ptr, k_idx, k_w
+
+    def update_graph(self, g):
+        self.update(g.out_ptr, g.out_idx, g.w)
+
+    def set_options(self, theta: float, inner_rounds: int = 0):
+        """New frontier scale (and local rounds, if > 0) for the following sweeps."""
+        _check(self._lib.di_set_sweep(self._ctx, float(theta), int(inner_rounds)))
 
     def reset(self):
         _check(self._lib.di_reset(self._ctx))

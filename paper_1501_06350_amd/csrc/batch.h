@@ -26,6 +26,8 @@ int read_batch(BatchState *b, const DevGraph &g, const SweepParams &p, int what,
                hipStream_t st);
 i64 batch_sweeps(BatchState *b, hipStream_t st);
 int batch_K(const BatchState *b);
+// local rounds of the tile's block-local sweeps (captured chunks are dropped)
+void set_batch_rounds(BatchState *b, int rounds);
 void free_batch(BatchState *b);
 
 }  // namespace di

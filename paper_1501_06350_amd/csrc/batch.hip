@@ -108,6 +108,14 @@ struct TileArgs {
     double d;
 };
 
+// the leak's sums are signed: the float fluid recomputed from H (F = F_0 + d P H - H) may be
+// slightly negative where the pushes' rounding let a node take more than its share
+__device__ __forceinline__ bool tile_leak_add(Limbs &a, double v, int K) {
+    if (!(v == v) || !(ldexp(fabs(v), K) < 0x1p126)) return false;
+    limbs_add_signed(a, v, K);
+    return true;
+}
+
 __device__ __forceinline__ bool tile_limbs_add(Limbs &a, double v, int K) {
     if (!(v == v) || !(ldexp(v, K) < 0x1p126)) return false;
     limbs_add(a, v, K);
@@ -211,7 +219,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
             nodes += lane == 0 ? 1 : 0;
             const i64 b = bb[u], e = __shfl(myptr, u + 1, WAVE);
             if (e == b) {
-                if (v != (T)0 && !tile_limbs_add(leak, fabs(f), a.K)) bad = 1;
+                if (v != (T)0 && !tile_leak_add(leak, f, a.K)) bad = 1;
                 continue;
             }
             const double q = (a.d * f) * __shfl(myinv, u, WAVE);
@@ -239,8 +247,8 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
 // Block-local fast sweep of the tile, in two kernels per sweep.
 //
 // k_tile_bld: node ids are grouped into ranges of 2^rb rows; a workgroup takes its
-// ranges one after another and keeps a range's fluid tile F[B][k] and the sweep's
-// history increments dH[B][k] (both of the fluid type) in LDS.  For a range it
+// ranges one after another and keeps a range's fluid tile F[B][k] (fluid type) and the
+// sweep's history increments dH[B][k] (double for every fluid type) in LDS.  For a range it
 //   1. stages the fluid rows (they already hold what other ranges sent last sweep);
 //   2. runs up to `rounds` local rounds: each wave scans its share of rows, takes a row
 //      when some running column reaches its threshold (every running column of the row
@@ -289,7 +297,7 @@ struct TileBldArgs {
 
 __host__ __device__ inline size_t tile_bld_lds(int rb, int k, int tsize) {
     const size_t B = (size_t)1 << rb;
-    return 2 * B * k * tsize + B * 4 + (B + 1) * 4;
+    return B * k * tsize + B * k * 8 + B * 4 + (B + 1) * 4;
 }
 
 // dynamic LDS of a launch: the tiles, and at least the per-column reduction scratch
@@ -310,7 +318,7 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
     const bool col = colk && !ctl->done[lane];
     const double thr = col ? ctl->thr[lane] : 0.0;
     T *Fl = reinterpret_cast<T *>(smem);
-    T *Dl = Fl + (size_t)B * k;
+    double *Dl = reinterpret_cast<double *>(Fl + (size_t)B * k);
     unsigned *Deg = reinterpret_cast<unsigned *>(Dl + (size_t)B * k);
     unsigned *Off = Deg + B;
     T *F = reinterpret_cast<T *>(a.F);
@@ -341,7 +349,7 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
                     const int e = e0 + u * TB_THREADS;
                     if (e < tot) {
                         Fl[e] = v[u];
-                        Dl[e] = (T)0;
+                        Dl[e] = 0.0;
                     }
                 }
             }
@@ -377,11 +385,11 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
                     const int i = i0 + u;
                     const T v = vv[u];
                     const double f = col && v != (T)0 ? (double)atomicExch(&Fl[i * k + lane], (T)0) : 0.0;
-                    if (f != 0.0) Dl[i * k + lane] += (T)f;
+                    if (f != 0.0) Dl[i * k + lane] += f;
                     nodes += lane == 0 ? 1 : 0;
                     const unsigned deg = Deg[i] & 0x7fffffffu;
                     if (deg == 0) {
-                        Ld += fabs(f);
+                        Ld += f;
                         continue;
                     }
                     const double q = (a.d * f) * (WTD ? a.inv_s[base + i] : 1.0 / (double)deg);
@@ -409,20 +417,21 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
         // rows with an increment) are all loaded before any is stored
         constexpr int WU = 4;
         for (int i0 = w * WU; i0 < cnt; i0 += TB_WAVES * WU) {
-            T vv[WU], dd[WU];
+            T vv[WU];
+            double dd[WU];
             double hv[WU], rwv[WU], invv[WU];
             unsigned df[WU];
 #pragma unroll
             for (int u = 0; u < WU; ++u) {
                 const int i = min(i0 + u, cnt - 1);
                 vv[u] = colk && i0 + u < cnt ? Fl[i * k + lane] : (T)0;
-                dd[u] = colk && i0 + u < cnt ? Dl[i * k + lane] : (T)0;
+                dd[u] = colk && i0 + u < cnt ? Dl[i * k + lane] : 0.0;
                 df[u] = i0 + u < cnt ? Deg[i] : 0u;
             }
 #pragma unroll
             for (int u = 0; u < WU; ++u) {
                 const i64 gi = base + min(i0 + u, cnt - 1);
-                hv[u] = dd[u] != (T)0 ? a.H[gi * k + lane] : 0.0;
+                hv[u] = dd[u] != 0.0 ? a.H[gi * k + lane] : 0.0;
                 const bool remote = (df[u] & 0x80000000u) != 0;
                 rwv[u] = remote ? a.rw[gi] : 0.0;
                 invv[u] = remote ? (WTD ? a.inv_s[gi] : 1.0 / (double)(df[u] & 0x7fffffffu)) : 0.0;
@@ -431,14 +440,15 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
             for (int u = 0; u < WU; ++u) {
                 if (i0 + u >= cnt) break;
                 const i64 gi = base + i0 + u;
-                const T v = vv[u], dh = dd[u];
+                const T v = vv[u];
+                const double dh = dd[u];
                 if (colk) F[gi * k + lane] = v;
-                if (dh != (T)0) a.H[gi * k + lane] = hv[u] + (double)dh;
+                if (dh != 0.0) a.H[gi * k + lane] = hv[u] + dh;
                 Rd += fabs((double)v);
                 const u64 vb = (u64)__double_as_longlong(fabs((double)v));
                 mx = vb > mx ? vb : mx;
                 if (df[u] & 0x80000000u) {
-                    const T s = dh != (T)0 ? (T)((a.d * (double)dh) * invv[u]) : (T)0;
+                    const T s = dh != 0.0 ? (T)((a.d * dh) * invv[u]) : (T)0;
                     const bool fl = __ballot(s != (T)0) != 0;
                     if (fl) {
                         if (colk) S[gi * k + lane] = s;
@@ -454,7 +464,7 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
     limbs_zero(R);
     limbs_zero(leak);
     if (!tile_limbs_add(R, Rd * (1.0 + 0x1p-30), a.K)) bad = 1;
-    if (!tile_limbs_add(leak, Ld, a.K)) bad = 1;
+    if (!tile_leak_add(leak, Ld, a.K)) bad = 1;
     // the per-column reductions reuse the tile's LDS (TB_WAVES * 64 * PSR words)
     u64 *red = reinterpret_cast<u64 *>(smem);
     u64 rv[PSR] = {R.l[0], R.l[1], R.l[2], R.l[3], mx};
@@ -569,7 +579,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_snapshot(TileArgs a) {
             F[slot] = (T)0;
             const double inv = a.inv_s[i];
             if (inv == 0.0) {
-                if (!tile_limbs_add(leak, fabs(f), a.K)) bad = 1;
+                if (!tile_leak_add(leak, f, a.K)) bad = 1;
             } else {
                 q = (a.d * f) * inv;
             }
@@ -968,6 +978,14 @@ static int refine_tile(BatchState *b, const DevGraph &g, const SweepParams &p, h
 
 int batch_K(const BatchState *b) { return b ? b->K : 0; }
 
+void set_batch_rounds(BatchState *b, int rounds) {
+    b->rounds = rounds;
+    if (b->gexec) {  // a captured chunk holds the old launch arguments
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+}
+
 void free_batch(BatchState *b) {
     if (!b) return;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -992,15 +1010,15 @@ static int load_batch_z(BatchState *b, const SweepParams &p, const double *Z) {
     std::vector<double> f0((size_t)(n * k));
     double mx = 0.0;
     for (int c = 0; c < k; ++c) {
-        double zs = 0.0;
+        HostSum zs;
         for (i64 i = 0; i < n; ++i) {
             const double z = Z ? Z[(i64)c * n + i] : 1.0 / (double)n;
-            zs += z;
+            zs.add(z);
             const double v = (1.0 - p.d) * z;
             f0[(size_t)(i * k + c)] = v;
             mx = std::max(mx, std::fabs(p.fp32 ? (double)(float)v : v));
         }
-        b->zsum[c] = zs;
+        b->zsum[c] = zs.value();
     }
     int e_max = 0;
     if (mx > 0.0) std::frexp(mx, &e_max);
@@ -1155,7 +1173,7 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
     if (!alloc(&b->F, n * k * T) || !alloc((void **)&b->F0, n * k * 8) || !alloc((void **)&b->H, n * k * 8) ||
         !alloc((void **)&b->ctl, sizeof(TileCtl)) || !alloc((void **)&b->partR, slots * KMAX * PSR * 8) ||
         !alloc((void **)&b->partC, slots * KMAX * 4 * 8) || !alloc((void **)&b->partK, slots * 2 * 8) ||
-        !alloc((void **)&b->partH, (size_t)b->gridR * KMAX * PSR * 8) || !alloc((void **)&b->hsum, KMAX * 8) ||
+        !alloc((void **)&b->partH, (size_t)b->gridR * KMAX * 4 * 8) || !alloc((void **)&b->hsum, 2 * KMAX * 8) ||
         (det && !alloc((void **)&b->snap, n * k * 8)))
         return fail(DI_ENOMEM);
     if (b->bld) {
@@ -1290,7 +1308,7 @@ int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const 
         double rmax = 0.0, lsum = 0.0, bn = 0.0;
         for (int c = 0; c < b->k; ++c) {
             rmax = std::max(rmax, h.R[c]);
-            const double l = limbs_to_double_raw(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
+            const double l = limbs_to_double_signed(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
             lsum += l;
             bn = std::max(bn, h.R[c] / (1.0 - p.d - p.d * l / b->zsum[c]));
         }
@@ -1313,7 +1331,24 @@ int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const 
     return DI_OK;
 }
 
-// One workgroup per column: add the column's limb slots of k_tile_reduce (run on H).
+// Exact signed per-column sums of an n x k node-major double or float tile into
+// per-workgroup slots part[block][column][0..3].
+template <typename T>
+__global__ void __launch_bounds__(TILE_THREADS) k_tile_sum_signed(const T *__restrict__ v, i64 n, int k, int K,
+                                                                  u64 *part) {
+    __shared__ u64 lds[TILE_WAVES * WAVE * 4];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    Limbs S;
+    limbs_zero(S);
+    if (lane < k) {
+        const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
+        for (i64 i = (i64)blockIdx.x * TILE_WAVES + w; i < n; i += nwaves) limbs_add_signed(S, (double)v[i * k + lane], K);
+    }
+    u64 q[4] = {S.l[0], S.l[1], S.l[2], S.l[3]};
+    block_columns_store<4>(q, lds, part + (i64)blockIdx.x * KMAX * 4, k);
+}
+
+// One workgroup per column: add the column's limb slots of k_tile_sum_signed.
 __global__ void __launch_bounds__(256) k_tile_colsum(const u64 *__restrict__ part, int nslots, int K, double *out) {
     __shared__ u64 red[4 * 4];
     __shared__ u64 tot[4];
@@ -1321,34 +1356,37 @@ __global__ void __launch_bounds__(256) k_tile_colsum(const u64 *__restrict__ par
     u64 v[4] = {0, 0, 0, 0};
     for (int q = threadIdx.x; q < nslots; q += blockDim.x)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] += part[((i64)q * KMAX + c) * PSR + t];
+        for (int t = 0; t < 4; ++t) v[t] += part[((i64)q * KMAX + c) * 4 + t];
     block_store_partials<4>(v, red, tot);
-    if (threadIdx.x == 0) out[c] = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], K);
+    if (threadIdx.x == 0) out[c] = limbs_to_double_signed(tot[0], tot[1], tot[2], tot[3], K);
 }
 
 int batch_mass_defects(BatchState *b, const DevGraph &g, const SweepParams &p, double *out, hipStream_t st) {
-    // the history of a column sums to at most |Z_c|_1 (x = (1-d)(I-dP)^{-1} Z_c, |P|_1 <= 1)
+    // the history and fluid sums of a column stay within a few times |Z_c|_1
+    // (x = (1-d)(I-dP)^{-1} Z_c and |P|_1 <= 1)
     double zmax = 0.0;
     for (int c = 0; c < b->k; ++c) zmax = std::max(zmax, b->zsum[c]);
     int e_max = 0, e_n = 0;
-    std::frexp(zmax, &e_max);
+    std::frexp(8.0 * zmax, &e_max);
     while (((i64)1 << e_n) < b->n) ++e_n;
     const int KH = 118 - (e_max + e_n);
-    TileArgs a = tile_args(b, g, p);
-    a.F = b->H;
-    a.K = KH;
-    a.partR = b->partH;
-    k_tile_reduce<double><<<b->gridR, TILE_THREADS, 0, st>>>(a, 1);
+    const unsigned grid = (unsigned)b->gridR;
+    k_tile_sum_signed<double><<<grid, TILE_THREADS, 0, st>>>(b->H, b->n, b->k, KH, b->partH);
     DI_LAUNCH_CHECK();
     k_tile_colsum<<<b->k, 256, 0, st>>>(b->partH, b->gridR, KH, b->hsum);
     DI_LAUNCH_CHECK();
-    std::vector<double> hs((size_t)b->k);
-    DI_HIP(hipMemcpyAsync(hs.data(), b->hsum, sizeof(double) * b->k, hipMemcpyDeviceToHost, st));
+    if (b->fp32) k_tile_sum_signed<float><<<grid, TILE_THREADS, 0, st>>>((const float *)b->F, b->n, b->k, KH, b->partH);
+    else k_tile_sum_signed<double><<<grid, TILE_THREADS, 0, st>>>((const double *)b->F, b->n, b->k, KH, b->partH);
+    DI_LAUNCH_CHECK();
+    k_tile_colsum<<<b->k, 256, 0, st>>>(b->partH, b->gridR, KH, b->hsum + KMAX);
+    DI_LAUNCH_CHECK();
+    std::vector<double> hs((size_t)(2 * KMAX));
+    DI_HIP(hipMemcpyAsync(hs.data(), b->hsum, sizeof(double) * 2 * KMAX, hipMemcpyDeviceToHost, st));
     DI_TRY(sync_tile(b, st));
     const TileCtl &h = *b->h_ctl;
     for (int c = 0; c < b->k; ++c) {
-        const double l = limbs_to_double_raw(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
-        out[c] = h.R[c] + (1.0 - p.d) * hs[c] + p.d * l - (1.0 - p.d) * b->zsum[c];
+        const double l = limbs_to_double_signed(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
+        out[c] = hs[KMAX + c] + (1.0 - p.d) * hs[c] + p.d * l - (1.0 - p.d) * b->zsum[c];
     }
     return DI_OK;
 }
@@ -1375,7 +1413,7 @@ int read_batch(BatchState *b, const DevGraph &g, const SweepParams &p, int what,
         for (int c = 0; c < k; ++c)
             v[c] = what == DI_RESIDUALS
                        ? h.R[c]
-                       : limbs_to_double_raw(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
+                       : limbs_to_double_signed(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
         return small(v.data(), sizeof(double) * k);
     }
     if (what != DI_X_RAW && what != DI_H && what != DI_F && what != DI_X_NORM) {
@@ -1388,7 +1426,7 @@ int read_batch(BatchState *b, const DevGraph &g, const SweepParams &p, int what,
         const TileCtl &h = *b->h_ctl;
         std::vector<double> sc((size_t)k);
         for (int c = 0; c < k; ++c) {
-            const double l = limbs_to_double_raw(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
+            const double l = limbs_to_double_signed(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
             sc[c] = (1.0 - p.d) / (1.0 - p.d - p.d * l / b->zsum[c]);
         }
         DI_HIP(hipMalloc((void **)&scale, sizeof(double) * k));

@@ -64,6 +64,7 @@ struct di_ctx {
     int rounds = 8;
     int spc = 8;  // sweeps per host check
     double zsum = 1.0;  // sum of Z (single right-hand side)
+    double f0max = 0.0; // largest starting fluid value (rounded to the fluid type)
     bool forward_converged = false;
     bool pi_ready = false;  // power-iteration buffers allocated
     bool pi_done = false;   // X_PI holds the result for the current Z
@@ -159,7 +160,8 @@ int sync_ctl(di_ctx *c, DevCtl *dctl) {
     return DI_OK;
 }
 
-double host_limbs(const u64 *l, int K) { return limbs_to_double_raw(l[0], l[1], l[2], l[3], K); }
+// the leak from its limb sums (signed: fluid may be negative after a graph update)
+double host_limbs(const u64 *l, int K) { return limbs_to_double_signed(l[0], l[1], l[2], l[3], K); }
 
 __global__ void k_ctl_begin(DevCtl *c, long long max_sweeps) {
     c->done = 0;
@@ -240,11 +242,17 @@ int enqueue_di_sweep(di_ctx *c, hipStream_t st, hipEvent_t e0 = nullptr, hipEven
     return enqueue_finalize(c, FIN_DI, st);
 }
 
-int enqueue_pi_iteration(di_ctx *c, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+// one power iteration on the iterates, x/s vectors and control block of s
+int enqueue_pi_iteration_on(di_ctx *c, SolveState &s, hipStream_t st, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr) {
     if (e0) DI_HIP(hipEventRecord(e0, st));
-    DI_TRY(launch_pi_iteration(c->g, c->rbin, c->s, c->p, st));
+    DI_TRY(launch_pi_iteration(c->g, c->rbin, s, c->p, st));
     if (e1) DI_HIP(hipEventRecord(e1, st));
-    return launch_finalize(c->s.pctl, c->p, FIN_PI, st, c->s.partR, c->s.nR, c->s.partC, 0);
+    return launch_finalize(s.pctl, c->p, FIN_PI, st, s.partR, s.nR, s.partC, 0);
+}
+
+int enqueue_pi_iteration(di_ctx *c, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    return enqueue_pi_iteration_on(c, c->s, st, e0, e1);
 }
 
 // After a synced chunk: add the device time of the steps that really ran.
@@ -365,8 +373,9 @@ int fill_stats_mg(di_ctx *c, di_stats *st, const DevCtl &h, const DevCtl &before
 // c->defects: sum F + (1-d) sum H + d l - (1-d) sum Z.  Equation HnFn gives
 // H + F = F_0 + d P H; summing its entries with 1^T P = 1^T - 1_D^T (the columns of P sum
 // to 1 except at dangling nodes, Section 2.1) leaves this sum at zero in exact
-// arithmetic.  sum F is the exact residual (fluid is nonnegative; in flight included),
-// sum H an exact fixed-point sum on the device; the stats get the largest magnitude.
+// arithmetic.  sum F and sum H are exact signed fixed-point sums on the device (the fluid
+// in flight has been delivered at the end of every call); the stats get the largest
+// magnitude.
 int mass_defects(di_ctx *c, di_stats *st) {
     const i64 G = c->s.range_graph ? c->n_graphs : 1;
     c->defects.assign((size_t)G, 0.0);
@@ -377,23 +386,25 @@ int mass_defects(di_ctx *c, di_stats *st) {
         double zmax = c->zsum;
         if (G > 1)
             for (i64 q = 0; q < G; ++q) zmax = std::max(zmax, c->h_ginfo[q].zsum);
-        // every history sum is at most the sum of its Z (|P|_1 <= 1), so a fixed-point scale
-        // for n values of size zmax cannot overflow
-        const int KH = fixed_scale(zmax, c->g.n);
-        DI_TRY(launch_sum_history(c->g, c->s, KH, c->s.partH, c->s.hsum, c->st));
-        std::vector<double> hs((size_t)G);
-        DI_HIP(hipMemcpyAsync(hs.data(), c->s.hsum, sizeof(double) * G, hipMemcpyDeviceToHost, c->st));
+        // history and fluid sums stay within a few times the sum of Z (|P|_1 <= 1, and the
+        // fluid only falls in L1 once a call has started), so a fixed-point scale for n
+        // values of size 8 zmax leaves room
+        const int KH = fixed_scale(8.0 * zmax, c->g.n);
+        DI_TRY(launch_node_sums(c->g, c->s, c->s.H, 0, KH, c->s.partH, c->s.hsum, c->st));
+        DI_TRY(launch_node_sums(c->g, c->s, c->s.F, c->p.fp32, KH, c->s.partH, c->s.hsum + G, c->st));
+        std::vector<double> hs((size_t)(2 * G));
+        DI_HIP(hipMemcpyAsync(hs.data(), c->s.hsum, sizeof(double) * 2 * G, hipMemcpyDeviceToHost, c->st));
         DI_TRY(sync_ctl(c, c->s.ctl));
         if (G > 1) {
             DI_TRY(sync_gctl(c));
             for (i64 q = 0; q < G; ++q) {
                 const GraphCtl &gc = c->h_gctl[q];
-                c->defects[q] = gc.R + (1.0 - c->d) * hs[q] + c->d * host_limbs(gc.limbsL, c->p.K) -
+                c->defects[q] = hs[G + q] + (1.0 - c->d) * hs[q] + c->d * host_limbs(gc.limbsL, c->p.K) -
                                 (1.0 - c->d) * c->h_ginfo[q].zsum;
             }
         } else {
             const DevCtl &h = *c->h_ctl;
-            c->defects[0] = h.R + (1.0 - c->d) * hs[0] + c->d * host_limbs(h.limbsL, c->p.K) - (1.0 - c->d) * c->zsum;
+            c->defects[0] = hs[1] + (1.0 - c->d) * hs[0] + c->d * host_limbs(h.limbsL, c->p.K) - (1.0 - c->d) * c->zsum;
         }
     }
     if (st) {
@@ -578,6 +589,58 @@ __global__ void k_seg_to_caller(const double *__restrict__ src, double *dst, con
     }
 }
 
+// caller array (n_user values) -> internal layout of cut-aligned ranges (padding gets 0)
+__global__ void k_caller_to_seg(const double *__restrict__ src, double *dst, const i64 *__restrict__ start, int rb,
+                                i64 n_int) {
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < n_int; q += (i64)gridDim.x * blockDim.x) {
+        const i64 r = q >> rb, j = q & (((i64)1 << rb) - 1);
+        dst[q] = j < start[r + 1] - start[r] ? src[start[r] + j] : 0.0;
+    }
+}
+
+// Theorem 4: F' = F + d (P'H - PH) in double, stored in the fluid type; the largest |F'|
+// (bits of a nonnegative double order like the double) into *maxbits
+template <typename T>
+__global__ void k_update_fluid(const double *__restrict__ F, const double *__restrict__ PH_new,
+                               const double *__restrict__ PH_old, double d, i64 n, T *Fout, u64 *maxbits) {
+    u64 mx = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const T f = (T)(F[i] + d * (PH_new[i] - PH_old[i]));
+        Fout[i] = f;
+        const u64 b = (u64)__double_as_longlong(fabs((double)f));
+        mx = b > mx ? b : mx;
+    }
+    mx = wave_max_u64(mx);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && mx) atomicMax(maxbits, mx);
+}
+
+// exact signed sum of H over the dangling nodes (1/s = 0) into per-workgroup limb slots
+__global__ void __launch_bounds__(256) k_dangling_history(const double *__restrict__ H, const double *__restrict__ inv_s,
+                                                          i64 n, int K, u64 *part) {
+    __shared__ u64 red[4 * 4];
+    Limbs S;
+    limbs_zero(S);
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+        if (inv_s[i] == 0.0) limbs_add_signed(S, H[i], K);
+    u64 w[4] = {S.l[0], S.l[1], S.l[2], S.l[3]};
+    block_store_partials<4>(w, red, part + (i64)blockIdx.x * PSR);
+}
+
+// the leak of the control block := the sum of the slots (normalised limbs)
+__global__ void __launch_bounds__(256) k_set_leak(DevCtl *ctl, const u64 *__restrict__ part, i64 nslots) {
+    __shared__ u64 red[4 * 4];
+    __shared__ u64 tot[4];
+    u64 v[4] = {0, 0, 0, 0};
+    for (i64 q = threadIdx.x; q < nslots; q += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += part[q * PSR + k];
+    block_store_partials<4>(v, red, tot);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 4; ++k) ctl->limbsL[k] = tot[k];
+        limbs_normalize(ctl->limbsL);
+    }
+}
+
 // caller array (n_user values) -> internal layout (padding gets fill)
 void seg_expand(const di_ctx *c, const double *src, double *dst, double fill) {
     const i64 B = (i64)1 << c->seg_rb, nr = (i64)c->seg_start.size() - 1;
@@ -739,7 +802,8 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     // their graph; Z (given, or uniform 1/n_g per graph) is laid out the same way
     std::vector<i64> pptr, gstart;
     std::vector<int> pidx;
-    std::vector<double> pz, gzsum;
+    std::vector<double> pz;
+    std::vector<HostSum> gzsum;
     const i64 n_user = n;
     if (opt.n_graphs > 1) {
         const i64 G = opt.n_graphs, B = (i64)1 << rb;
@@ -752,7 +816,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         pptr.assign((size_t)n2 + 1, 0);
         pidx.resize((size_t)std::max<i64>(m, 1));
         pz.assign((size_t)n2, 0.0);
-        gzsum.assign((size_t)G, 0.0);
+        gzsum.assign((size_t)G, HostSum());
         for (i64 q = 0; q < G; ++q) {
             const i64 lo = gp[q], hi = gp[q + 1], ng = hi - lo;
             for (i64 u = 0; u < gstart[q + 1] - gstart[q]; ++u) pptr[gstart[q] + u] = ptr[lo + std::min(u, ng)];
@@ -764,9 +828,9 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
             for (i64 u = 0; u < ng; ++u) {
                 const double z = Z ? Z[lo + u] : 1.0 / (double)ng;
                 pz[gstart[q] + u] = z;
-                gzsum[q] += z;
+                gzsum[q].add(z);
             }
-            if (!(gzsum[q] > 0.0)) DI_FAIL(DI_EINVAL, "Z sums to zero on graph %lld", (long long)q);
+            if (!(gzsum[q].value() > 0.0)) DI_FAIL(DI_EINVAL, "Z sums to zero on graph %lld", (long long)q);
         }
         pptr[n2] = m;
         n = n2;
@@ -886,7 +950,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     {
         const i64 slots = std::max<i64>(c->g.nranges, PART_MIN);
         if ((rc = dalloc(c, &c->s.partR, slots * PSR)) || (rc = dalloc(c, &c->s.partC, slots * PSC)) ||
-            (rc = dalloc(c, &c->s.partH, slots * PSR)) || (rc = dalloc(c, &c->s.hsum, std::max<i64>(opt.n_graphs, 1))))
+            (rc = dalloc(c, &c->s.partH, slots * PSR)) || (rc = dalloc(c, &c->s.hsum, 2 * std::max<i64>(opt.n_graphs, 1))))
             return fail(rc);
     }
 
@@ -901,8 +965,11 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     const size_t T = c->p.fp32 ? 4 : 8;
     std::vector<double> f0((size_t)n);
     double mx = 0.0;
-    c->zsum = 0.0;
-    for (i64 i = 0; i < n; ++i) c->zsum += Z ? Z[i] : 1.0 / (double)n;
+    {
+        HostSum zs;
+        for (i64 i = 0; i < n; ++i) zs.add(Z ? Z[i] : 1.0 / (double)n);
+        c->zsum = zs.value();
+    }
     c->p.zsum = c->zsum;
     // F_0 is kept in double; the fluid starts from it rounded to the fluid type
     for (i64 i = 0; i < n; ++i) {
@@ -912,6 +979,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         mx = std::max(mx, std::fabs(c->p.fp32 ? (double)(float)v : v));
     }
     c->p.K = fixed_scale(mx, n);
+    c->f0max = mx;
     // in-flight buffers: n values, then a bitmap of the nonzero ones (n/64 words)
     const i64 s_vals = ((i64)(n * T) + 255) & ~(i64)255;
     c->s.S_bytes = s_vals + ((n + 63) / 64) * 8;
@@ -940,7 +1008,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
             gi.rbeg = c->gstart[q] >> rb;
             gi.rend = c->gstart[q + 1] >> rb;
             gi.n_d = (double)(c->graph_ptr[q + 1] - c->graph_ptr[q]);
-            gi.zsum = gzsum[q];
+            gi.zsum = gzsum[q].value();
             for (i64 r = gi.rbeg; r < gi.rend; ++r) c->h_range_graph[r] = (int)q;
         }
         std::vector<double> ones((size_t)G, 1.0);
@@ -958,8 +1026,30 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         c->s.n_graphs = G;
         c->s.rb = rb;
     }
+    // one graph: the IN row blocks of power iteration (and of the float fluid's
+    // recomputation and the graph update) are built here
+    if (c->n_graphs == 1 && (rc = ensure_row_blocks(c)) != DI_OK) return fail(rc);
     if ((rc = reset_state(c)) != DI_OK) return fail(rc);
     *out = c;
+    return DI_OK;
+}
+
+int di_set_sweep(di_ctx *c, double theta, int inner_rounds) {
+    if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
+    if (!(theta >= 0.0) || !std::isfinite(theta)) DI_FAIL(DI_EINVAL, "theta must be finite and >= 0");
+    if (inner_rounds < 0 || inner_rounds > 64) DI_FAIL(DI_EINVAL, "inner_rounds must be in 0..64");
+    c->p.theta = theta;
+    c->o.theta = theta;
+    if (inner_rounds > 0) {
+        c->rounds = inner_rounds;
+        c->p.rounds = inner_rounds;
+        c->o.inner_rounds = inner_rounds;
+        if (c->b) set_batch_rounds(c->b, inner_rounds);
+    }
+    if (c->gexec) {  // captured chunks hold the old threshold scale and rounds
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
     return DI_OK;
 }
 
@@ -988,16 +1078,17 @@ int di_set_z(di_ctx *c, const double *Z) {
     c->defects.clear();
     if (c->b) return set_batch_z(c->b, c->g, c->p, Z, c->st);
     // layout of the context (padded per graph in a union), F_0 = (1-d) Z in double
-    std::vector<double> f0((size_t)n, 0.0), gz((size_t)c->n_graphs, 0.0);
+    std::vector<double> f0((size_t)n, 0.0);
+    std::vector<HostSum> gz((size_t)c->n_graphs);
     if (c->n_graphs > 1) {
         for (i64 q = 0; q < c->n_graphs; ++q) {
             const i64 lo = c->graph_ptr[q], ng = c->graph_ptr[q + 1] - lo;
             for (i64 u = 0; u < ng; ++u) {
                 const double z = Z ? Z[lo + u] : 1.0 / (double)ng;
                 f0[c->gstart[q] + u] = z;
-                gz[q] += z;
+                gz[q].add(z);
             }
-            if (!(gz[q] > 0.0)) DI_FAIL(DI_EINVAL, "Z sums to zero on graph %lld", (long long)q);
+            if (!(gz[q].value() > 0.0)) DI_FAIL(DI_EINVAL, "Z sums to zero on graph %lld", (long long)q);
         }
     } else if (c->seg) {  // cut-aligned ranges: padding nodes get no Z
         std::vector<double> zu;
@@ -1008,9 +1099,10 @@ int di_set_z(di_ctx *c, const double *Z) {
     }
     std::vector<double> zint;  // Z in the internal layout, for power iteration
     if (c->seg) zint = f0;
-    double zsum = 0.0, mx = 0.0;
+    double mx = 0.0;
+    HostSum zacc;
     for (i64 i = 0; i < n; ++i) {
-        zsum += f0[i];
+        zacc.add(f0[i]);
         f0[i] = (1.0 - c->d) * f0[i];
         mx = std::max(mx, std::fabs(c->p.fp32 ? (double)(float)f0[i] : f0[i]));
     }
@@ -1024,13 +1116,14 @@ int di_set_z(di_ctx *c, const double *Z) {
         }
         c->s.zc = (1.0 - c->d) * (1.0 / (double)n);  // read when s.Z is null (uniform Z)
     } else {
-        for (i64 q = 0; q < c->n_graphs; ++q) c->h_ginfo[q].zsum = gz[q];
+        for (i64 q = 0; q < c->n_graphs; ++q) c->h_ginfo[q].zsum = gz[q].value();
         DI_HIP(hipMemcpy(c->s.ginfo, c->h_ginfo.data(), sizeof(GraphInfo) * c->n_graphs, hipMemcpyHostToDevice));
     }
     DI_HIP(hipMemcpy(c->s.F0, f0.data(), sizeof(double) * n, hipMemcpyHostToDevice));
-    c->zsum = zsum;
-    c->p.zsum = zsum;
+    c->zsum = zacc.value();
+    c->p.zsum = c->zsum;
     c->p.K = fixed_scale(mx, n);
+    c->f0max = mx;
     c->pi_done = false;
     if (c->gexec) {  // a captured chunk holds the old fixed-point scale
         (void)hipGraphExecDestroy(c->gexec);
@@ -1590,6 +1683,123 @@ struct CkptHeader {
     double d;
 };
 }  // namespace
+
+int di_update(di_ctx *c, const di_csr *g) {
+    if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
+    if (!g) DI_FAIL(DI_EINVAL, "graph is NULL");
+    if (c->b || c->n_graphs > 1) DI_FAIL(DI_EINVAL, "di_update supports one right-hand side on one graph");
+    if (g->n != c->n_user)
+        DI_FAIL(DI_EINVAL, "the new graph must keep the %lld nodes (got n = %lld)", (long long)c->n_user, (long long)g->n);
+    const i64 nu = c->n_user, n = c->g.n;
+    const int ordered = c->o.deterministic ? 1 : 0;
+    // device temporaries: H, F and P H of the current state in the caller's numbering, and
+    // two internal-layout vectors (reused for the new graph's layout)
+    double *tH = nullptr, *tF = nullptr, *tP = nullptr, *w0 = nullptr, *w1 = nullptr, *w2 = nullptr;
+    di_ctx *c2 = nullptr;
+    u64 *maxbits = nullptr;
+    auto release = [&]() {
+        for (void *q : {(void *)tH, (void *)tF, (void *)tP, (void *)w0, (void *)w1, (void *)w2, (void *)maxbits})
+            if (q) (void)hipFree(q);
+        if (c2) di_destroy(c2);
+    };
+    auto body = [&]() -> int {
+        DI_HIP(hipMalloc((void **)&tH, sizeof(double) * nu));
+        DI_HIP(hipMalloc((void **)&tF, sizeof(double) * nu));
+        DI_HIP(hipMalloc((void **)&tP, sizeof(double) * nu));
+        DI_HIP(hipMalloc((void **)&w0, sizeof(double) * n));
+        DI_HIP(hipMalloc((void **)&w1, sizeof(double) * n));
+        DI_HIP(hipMalloc((void **)&maxbits, sizeof(u64)));
+        auto to_caller = [&](const double *src, double *dst) -> int {
+            if (c->seg) {
+                k_seg_to_caller<<<grid_for(n, 256, 16384), 256, 0, c->st>>>(src, dst, c->d_seg_start, c->seg_rb, n);
+                DI_LAUNCH_CHECK();
+            } else {
+                DI_HIP(hipMemcpyAsync(dst, src, sizeof(double) * nu, hipMemcpyDeviceToDevice, c->st));
+            }
+            return DI_OK;
+        };
+        // P H on the current graph, then H, F, P H in the caller's numbering
+        DI_TRY(launch_P_times(c->g, c->rbin, c->s.H, w0, w1, ordered, c->st));
+        DI_TRY(to_caller(w1, tP));
+        DI_TRY(to_caller(c->s.H, tH));
+        DI_TRY(launch_copy_fluid_to_double(c->s.F, c->p.fp32, n, w0, c->st));
+        DI_TRY(to_caller(w0, tF));
+        // Z in the caller's numbering for the new context (NULL: uniform)
+        std::vector<double> zc;
+        if (c->s.Z) {
+            std::vector<double> zi((size_t)n);
+            DI_HIP(hipMemcpyAsync(zi.data(), c->s.Z, sizeof(double) * n, hipMemcpyDeviceToHost, c->st));
+            DI_HIP(hipStreamSynchronize(c->st));
+            zc.resize((size_t)nu);
+            seg_compact(c, zi.data(), zc.data());
+        }
+        DI_HIP(hipStreamSynchronize(c->st));
+        (void)hipFree(w0);
+        (void)hipFree(w1);
+        w0 = w1 = nullptr;
+        // the new graph, with the same d, Z and options (its own layout and row blocks)
+        di_opts o = c->o;
+        o.k = 1;
+        o.n_graphs = 1;
+        o.graph_ptr = nullptr;
+        DI_TRY(di_init(&c2, g, c->d, c->s.Z ? zc.data() : nullptr, &o));
+        const i64 n2 = c2->g.n;
+        DI_HIP(hipMalloc((void **)&w0, sizeof(double) * n2));
+        DI_HIP(hipMalloc((void **)&w1, sizeof(double) * n2));
+        DI_HIP(hipMalloc((void **)&w2, sizeof(double) * n2));
+        auto from_caller = [&](const double *src, double *dst) -> int {
+            if (c2->seg) {
+                k_caller_to_seg<<<grid_for(n2, 256, 16384), 256, 0, c2->st>>>(src, dst, c2->d_seg_start, c2->seg_rb, n2);
+                DI_LAUNCH_CHECK();
+            } else {
+                DI_HIP(hipMemcpyAsync(dst, src, sizeof(double) * nu, hipMemcpyDeviceToDevice, c2->st));
+            }
+            return DI_OK;
+        };
+        // Theorem 4: H' = H, F' = F + d (P' - P) H, evaluated as P'H - PH
+        DI_TRY(from_caller(tH, c2->s.H));
+        DI_TRY(launch_P_times(c2->g, c2->rbin, c2->s.H, w2, w1, ordered, c2->st));  // w1 = P'H
+        DI_TRY(from_caller(tF, w0));
+        DI_TRY(from_caller(tP, w2));  // w2 = P H
+        DI_TRY(launch_fill_zero(maxbits, sizeof(u64), c2->st));
+        if (c2->p.fp32)
+            k_update_fluid<float><<<grid_for(n2, 256, 16384), 256, 0, c2->st>>>(w0, w1, w2, c2->d, n2,
+                                                                               (float *)c2->s.F, maxbits);
+        else
+            k_update_fluid<double><<<grid_for(n2, 256, 16384), 256, 0, c2->st>>>(w0, w1, w2, c2->d, n2,
+                                                                                (double *)c2->s.F, maxbits);
+        DI_LAUNCH_CHECK();
+        u64 mb = 0;
+        DI_HIP(hipMemcpyAsync(&mb, maxbits, sizeof(u64), hipMemcpyDeviceToHost, c2->st));
+        DI_HIP(hipStreamSynchronize(c2->st));
+        double mxf = 0.0;
+        std::memcpy(&mxf, &mb, sizeof(double));
+        // the fixed-point scale covers the new fluid and the starting fluid (which bounds the
+        // leak); the leak restarts as the history at the nodes dangling in P' (the fluid
+        // those diffusions lose under P', Section 3.3)
+        c2->p.K = fixed_scale(std::max(c2->f0max, mxf), n2);
+        DI_TRY(launch_fill_zero(c2->s.S[0], c2->s.S_bytes, c2->st));
+        DI_TRY(launch_fill_zero(c2->s.S[1], c2->s.S_bytes, c2->st));
+        DI_TRY(launch_fill_zero(c2->s.ctl, sizeof(DevCtl), c2->st));
+        const unsigned gl = grid_for(n2, 256, REDUCE_GRID);
+        k_dangling_history<<<gl, 256, 0, c2->st>>>(c2->s.H, c2->g.inv_s, n2, c2->p.K, c2->s.partH);
+        DI_LAUNCH_CHECK();
+        k_set_leak<<<1, 256, 0, c2->st>>>(c2->s.ctl, c2->s.partH, gl);
+        DI_LAUNCH_CHECK();
+        DI_TRY(launch_reduce_F(c2->g, c2->s, c2->p, c2->st));
+        DI_TRY(enqueue_finalize(c2, FIN_INIT, c2->st));
+        DI_TRY(sync_ctl(c2, c2->s.ctl));
+        if (c2->h_ctl->overflow) DI_FAIL(DI_ENUMERIC, "non-finite fluid after the update");
+        // the context takes the new graph and state; the old ones are released with c2
+        std::swap(*c, *c2);
+        c->forward_converged = false;
+        c->defects.clear();
+        return DI_OK;
+    };
+    const int rc = body();
+    release();
+    return rc;
+}
 
 int di_save(di_ctx *c, const char *path) {
     if (!c || !path) DI_FAIL(DI_EINVAL, "NULL argument");

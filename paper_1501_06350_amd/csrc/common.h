@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -46,6 +47,19 @@ inline unsigned grid_for(i64 work, int per_block, i64 cap = (1ll << 30)) {
     return (unsigned)g;
 }
 
+// Host sum of many doubles with a running compensation (Neumaier's variant of Kahan's
+// summation): the error stays at a few units in the last place of the result instead of
+// growing with the count (the sum of Z over 10^8 nodes of 1/n each, for instance).
+struct HostSum {
+    double s = 0.0, c = 0.0;
+    void add(double x) {
+        const double t = s + x;
+        c += std::fabs(s) >= std::fabs(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    double value() const { return s + c; }
+};
+
 // ---------------------------------------------------------------------------
 // Fixed-point residual sums.  A non-negative double v contributes floor(v * 2^K);
 // the sum is kept exactly in four 64-bit accumulators of 32-bit limbs, so it does
@@ -68,6 +82,32 @@ __device__ __forceinline__ void limbs_add(Limbs &a, double v, int K) {
         s = s - (double)hi * 0x1p64;   // exact: the bits of s below 2^64
     }
     u64 lo = (u64)s;
+    a.l[0] += lo & 0xffffffffull;
+    a.l[1] += lo >> 32;
+    a.l[2] += hi & 0xffffffffull;
+    a.l[3] += hi >> 32;
+}
+
+// Signed values: the accumulator holds its sum modulo 2^128 (two's complement); a negative
+// v adds the 32-bit pieces of 2^128 - floor(|v| 2^K).  Sums stay below 2^118 in magnitude,
+// so bit 127 of the carried value tells the sign (limbs_to_double_signed).
+__device__ __forceinline__ void limbs_add_signed(Limbs &a, double v, int K) {
+    if (v > 0.0) {
+        limbs_add(a, v, K);
+        return;
+    }
+    if (!(v < 0.0)) return;
+    double s = ldexp(-v, K);
+    u64 hi = 0;
+    if (s >= 0x1p64) {
+        hi = (u64)(s * 0x1p-64);
+        s = s - (double)hi * 0x1p64;
+    }
+    u64 lo = (u64)s;
+    if ((lo | hi) == 0) return;
+    // two's complement of (hi, lo)
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0 ? 1ull : 0ull);
     a.l[0] += lo & 0xffffffffull;
     a.l[1] += lo >> 32;
     a.l[2] += hi & 0xffffffffull;
@@ -162,8 +202,8 @@ __host__ __device__ inline void limbs_normalize(u64 *l) {
     l[3] += c;
 }
 
-__host__ __device__ inline double limbs_to_double_raw(u64 l0, u64 l1, u64 l2, u64 l3, int K) {
-    // carry-propagate into a 128-bit value (hi, lo)
+// carry-propagate limb sums into a 128-bit value (hi, lo), modulo 2^128
+__host__ __device__ inline void limbs_to_u128(u64 l0, u64 l1, u64 l2, u64 l3, u64 *hi_out, u64 *lo_out) {
     u64 lo = l0 & 0xffffffffull, c = l0 >> 32;
     u64 t = l1 + c;
     u64 carry_hi = (t < l1) ? 1ull : 0ull;  // overflow into bit 96
@@ -175,6 +215,12 @@ __host__ __device__ inline double limbs_to_double_raw(u64 l0, u64 l1, u64 l2, u6
     c = (t >> 32) | (c2 << 32);
     t = l3 + c;
     hi |= t << 32;
+    *hi_out = hi;
+    *lo_out = lo;
+}
+
+// a nonnegative 128-bit integer (hi, lo) times 2^-K, rounded once to the nearest double
+__host__ __device__ inline double u128_to_double(u64 hi, u64 lo, int K) {
     if (hi == 0 && lo < (1ull << 53)) return ldexp((double)lo, -K);
     int p;  // index of the top set bit
     if (hi) p = 64 + 63 - __builtin_clzll(hi);
@@ -195,6 +241,24 @@ __host__ __device__ inline double limbs_to_double_raw(u64 l0, u64 l1, u64 l2, u6
     }
     if (round_bit && (sticky || (mant & 1ull))) mant += 1;
     return ldexp((double)mant, s - K);
+}
+
+__host__ __device__ inline double limbs_to_double_raw(u64 l0, u64 l1, u64 l2, u64 l3, int K) {
+    u64 hi, lo;
+    limbs_to_u128(l0, l1, l2, l3, &hi, &lo);
+    return u128_to_double(hi, lo, K);
+}
+
+// the same for a two's-complement signed sum (see limbs_add_signed)
+__host__ __device__ inline double limbs_to_double_signed(u64 l0, u64 l1, u64 l2, u64 l3, int K) {
+    u64 hi, lo;
+    limbs_to_u128(l0, l1, l2, l3, &hi, &lo);
+    if (hi >> 63) {  // negative: magnitude = 2^128 - value
+        lo = ~lo + 1ull;
+        hi = ~hi + (lo == 0 ? 1ull : 0ull);
+        return -u128_to_double(hi, lo, K);
+    }
+    return u128_to_double(hi, lo, K);
 }
 
 // ---------------------------------------------------------------------------

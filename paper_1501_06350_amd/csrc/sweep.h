@@ -79,7 +79,8 @@ struct SolveState {
     GraphInfo *ginfo = nullptr;  // n_graphs
     GraphCtl *gctl = nullptr;    // n_graphs
     i64 n_graphs = 0;
-    // exact sums of H per graph (mass balance): limb slots and one double per graph
+    // exact sums of H and of F per graph (mass balance): limb slots, then per graph
+    // the sum of H and the sum of F (2 n_graphs doubles)
     u64 *partH = nullptr;
     double *hsum = nullptr;
     int rb = 0;
@@ -121,6 +122,11 @@ int launch_pi_init(const DevGraph &g, SolveState &s, const SweepParams &p, hipSt
 // type (ht: n doubles of scratch); no residual
 int launch_refine_fluid(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, double *ht,
                         hipStream_t st);
+// out = P v (n doubles); ordered: a left fold over each IN row in source order (the
+// oracle's order, bit-reproducible), else the wave-parallel row pull over the row blocks
+// (ht: n doubles of scratch for v / s)
+int launch_P_times(const DevGraph &g, const RowBlocks &rb, const double *v, double *ht, double *out, int ordered,
+                   hipStream_t st);
 int launch_fill_zero(void *p, i64 bytes, hipStream_t st);
 // F = F0 rounded to the fluid type (count entries)
 int launch_init_fluid(const double *F0, void *F, int fp32, i64 count, hipStream_t st);
@@ -146,9 +152,10 @@ int launch_adj_sweep(const DevGraph &g, double *F, double *H, double *snap, DevC
 // row blocks of OUT) that also sums the residual; additions in lane order, not row order.
 int launch_adj_sweep_fast(const DevGraph &g, const RowBlocks &rb_out, double *F, double *H, double *snap, DevCtl *ctl,
                           const SweepParams &p, hipStream_t st, u64 *partR, u64 *partC, i64 *nR, i64 *nC);
-// exact sum of H per graph of a union (else one sum) on 2^-K into out[0 .. n_graphs);
-// part: max(nranges, PART_MIN) * PSR words of scratch
-int launch_sum_history(const DevGraph &g, SolveState &s, int K, u64 *part, double *out, hipStream_t st);
+// exact signed sum of a node vector v (n values, float or double) per graph of a union
+// (else one sum) on 2^-K into out[0 .. n_graphs); part: max(nranges, PART_MIN) * PSR words
+int launch_node_sums(const DevGraph &g, SolveState &s, const void *v, int is_float, int K, u64 *part, double *out,
+                     hipStream_t st);
 int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR);
 int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
                      hipStream_t st);

@@ -72,6 +72,13 @@ __device__ __forceinline__ bool limbs_add_checked(Limbs &a, double v, int K) {
     return true;
 }
 
+// the same for a signed value (the leak: fluid is signed after a graph update)
+__device__ __forceinline__ bool limbs_add_signed_checked(Limbs &a, double v, int K) {
+    if (!(v == v) || !(ldexp(fabs(v), K) < 0x1p126)) return false;
+    limbs_add_signed(a, v, K);
+    return true;
+}
+
 struct BldArgs {
     const i64 *loc_ptr;
     const unsigned short *loc_tgt;
@@ -214,7 +221,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
                 a.H[gi] += f;
                 const double inv = a.inv_s[gi];
                 if (inv == 0.0) {
-                    if (!limbs_add_checked(leak, fabs(f), a.K)) bad = 1;
+                    if (!limbs_add_signed_checked(leak, f, a.K)) bad = 1;
                 } else {
                     q = (a.d * f) * inv;
                     if (a.rw[gi] > 0.0) Sl[i] = (T)((double)Sl[i] + q);
@@ -596,7 +603,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             if (f != 0.0) {
                 atomicAdd(&Dl[i], f);
                 if (deg == 0) {
-                    Ld += fabs(f);
+                    Ld += f;
                 } else {
                     q = (a.d * f) * rdeg;
                     st = o0;
@@ -705,7 +712,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     if (!limbs_add_checked(R, Rd * (1.0 + 0x1p-40), a.K)) bad = 1;
     Limbs leak;
     limbs_zero(leak);
-    if (!limbs_add_checked(leak, Ld, a.K)) bad = 1;
+    if (!limbs_add_signed_checked(leak, Ld, a.K)) bad = 1;
     store_residual_partial(R, 0, red, a.partR + (i64)r * PSR);
     store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)r * PSC);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
@@ -819,7 +826,7 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinArgs a) {
     const double R = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], a.K);
     for (int k = 0; k < 4; ++k) c->limbsL[k] += tot[5 + k];
     limbs_normalize(c->limbsL);
-    const double l = limbs_to_double_raw(c->limbsL[0], c->limbsL[1], c->limbsL[2], c->limbsL[3], a.K);
+    const double l = limbs_to_double_signed(c->limbsL[0], c->limbsL[1], c->limbsL[2], c->limbsL[3], a.K);
     const double mx = __longlong_as_double((long long)tot[4]);
     const u64 nodes = tot[9], edges = tot[10], remote = tot[11];
     c->R = R;
@@ -932,7 +939,7 @@ __global__ void __launch_bounds__(FIN_THREADS) k_mg_finalize(MgFinArgs a) {
     const double R = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], a.K);
     for (int k = 0; k < 4; ++k) gc.limbsL[k] += tot[5 + k];
     limbs_normalize(gc.limbsL);
-    const double l = limbs_to_double_raw(gc.limbsL[0], gc.limbsL[1], gc.limbsL[2], gc.limbsL[3], a.K);
+    const double l = limbs_to_double_signed(gc.limbsL[0], gc.limbsL[1], gc.limbsL[2], gc.limbsL[3], a.K);
     const double mx = __longlong_as_double((long long)tot[4]);
     const u64 nodes = tot[9];
     gc.nodes = nodes;
@@ -1083,10 +1090,22 @@ int launch_reduce_F(const DevGraph &g, SolveState &s, const SweepParams &p, hipS
     return DI_OK;
 }
 
-// Exact sum of the history per graph (one graph: one sum), for the mass balance
-// sum F + (1-d) sum H + d l = (1-d) sum Z that equation HnFn implies (the columns of P
-// sum to 1 except at dangling nodes, Section 2.1).  k_reduce_F leaves per-workgroup limb
-// slots (one per range in a union of graphs); one workgroup per graph adds its slots.
+// Exact signed sums of a node vector per graph (one graph: one sum), for the mass balance
+// sum F + (1-d) sum H + d l = (1-d) sum Z that equation HnFn implies (the columns of P sum
+// to 1 except at dangling nodes, Section 2.1).  Per-workgroup two's-complement limb slots
+// (one per range in a union of graphs), then one workgroup per graph adds its slots.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sum_signed(const T *__restrict__ v, i64 n, int K, u64 *part,
+                                                    const int *range_graph, int rb) {
+    __shared__ u64 red[4 * 4];
+    Limbs S;
+    limbs_zero(S);
+    const NodeLoop L = node_loop(n, range_graph, rb);
+    for (i64 i = L.i0; i < L.i1; i += L.step) limbs_add_signed(S, (double)v[i], K);
+    u64 w[4] = {S.l[0], S.l[1], S.l[2], S.l[3]};
+    block_store_partials<4>(w, red, part + (i64)blockIdx.x * PSR);
+}
+
 __global__ void __launch_bounds__(256) k_sum_slots(const u64 *__restrict__ part, i64 nslots,
                                                    const GraphInfo *__restrict__ gi, int K, double *out) {
     __shared__ u64 red[4 * 4];
@@ -1101,12 +1120,14 @@ __global__ void __launch_bounds__(256) k_sum_slots(const u64 *__restrict__ part,
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] += part[q * PSR + k];
     block_store_partials<4>(v, red, tot);
-    if (threadIdx.x == 0) out[blockIdx.x] = limbs_to_double_raw(tot[0], tot[1], tot[2], tot[3], K);
+    if (threadIdx.x == 0) out[blockIdx.x] = limbs_to_double_signed(tot[0], tot[1], tot[2], tot[3], K);
 }
 
-int launch_sum_history(const DevGraph &g, SolveState &s, int K, u64 *part, double *out, hipStream_t st) {
+int launch_node_sums(const DevGraph &g, SolveState &s, const void *v, int is_float, int K, u64 *part, double *out,
+                     hipStream_t st) {
     const unsigned grid = s.range_graph ? (unsigned)g.nranges : grid_for(g.n, 256, REDUCE_GRID);
-    k_reduce_F<double><<<grid, 256, 0, st>>>(s.H, g.n, K, s.ctl, part, s.range_graph, s.gctl, g.rb, 0);
+    if (is_float) k_sum_signed<float><<<grid, 256, 0, st>>>((const float *)v, g.n, K, part, s.range_graph, g.rb);
+    else k_sum_signed<double><<<grid, 256, 0, st>>>((const double *)v, g.n, K, part, s.range_graph, g.rb);
     DI_LAUNCH_CHECK();
     const unsigned G = s.range_graph ? (unsigned)s.n_graphs : 1u;
     k_sum_slots<<<G, 256, 0, st>>>(part, grid, s.range_graph ? s.ginfo : nullptr, K, out);
@@ -1149,7 +1170,7 @@ __global__ void __launch_bounds__(256) k_det_snapshot(T *F, double *H, double *s
             H[i] += f;
             F[i] = (T)0;
             const double inv = inv_s[i];
-            if (inv == 0.0) limbs_add(leak, fabs(f), K);
+            if (inv == 0.0) limbs_add_signed(leak, f, K);
             else q = (d * f) * inv;
             ++nodes;
             edges += (u64)(out_ptr[i + 1] - out_ptr[i]);
@@ -1236,7 +1257,7 @@ int launch_det_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, hip
 // additions is not the row order, so it is the fast adjoint, not the reproducible one).
 // ---------------------------------------------------------------------------
 constexpr int PI_WAVES = 4;
-constexpr int PM_PI = 0, PM_REF = 1, PM_ADJ = 2;
+constexpr int PM_PI = 0, PM_REF = 1, PM_ADJ = 2, PM_PROD = 3;
 
 struct PiArgs {
     const i64 *rb_start;
@@ -1264,12 +1285,13 @@ struct PiArgs {
     void *Fout;
 };
 
-// TX: type of the gathered values; MODE: PM_PI, PM_REF (always runs) or PM_ADJ
+// TX: type of the gathered values; MODE: PM_PI, PM_REF (always runs), PM_ADJ or PM_PROD
+// (always runs)
 template <typename TX, bool WTD, int MODE>
 __global__ void __launch_bounds__(256) k_pi_segments(PiArgs a) {
     __shared__ double red[256 / WAVE];
     DevCtl *ctl = a.ctl;
-    if (MODE != PM_REF && (ctl->done || ctl->sweep >= ctl->budget)) return;
+    if (MODE != PM_REF && MODE != PM_PROD && (ctl->done || ctl->sweep >= ctl->budget)) return;
     const TX *xt = MODE != PM_PI ? reinterpret_cast<const TX *>(a.ht)
                                  : reinterpret_cast<const TX *>(ctl->parity ? a.XT1 : a.XT0);
     const i64 sg = blockIdx.x;
@@ -1300,16 +1322,17 @@ __global__ void __launch_bounds__(256) k_pi_segments(PiArgs a) {
 }
 
 // T: type of x / s in power iteration, of the fluid in the recomputation (PM_REF);
-// the adjoint pull (PM_ADJ) is double throughout
+// the adjoint pull (PM_ADJ) and the plain product (PM_PROD: out = P v with ht = v / s)
+// are double throughout
 template <typename T, bool WTD, int MODE>
 __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
-    constexpr bool REF = MODE == PM_REF, ADJ = MODE == PM_ADJ;
+    constexpr bool REF = MODE == PM_REF, ADJ = MODE == PM_ADJ, PROD = MODE == PM_PROD;
     using TX = typename std::conditional<MODE != PM_PI, double, T>::type;
     __shared__ double tile[PI_WAVES][RB_NNZ];
     __shared__ u64 red[PSR * PI_WAVES];
     __shared__ int bad;
     DevCtl *ctl = a.ctl;
-    if (!REF && (ctl->done || ctl->sweep >= ctl->budget)) return;
+    if (!REF && !PROD && (ctl->done || ctl->sweep >= ctl->budget)) return;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     const int par = MODE != PM_PI ? 0 : ctl->parity;
@@ -1382,7 +1405,9 @@ __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
             }
         }
         if (row >= 0) {
-            if (REF) {
+            if (PROD) {
+                reinterpret_cast<double *>(a.Fout)[row] = acc;
+            } else if (REF) {
                 const double f = (a.F0[row] + a.d * acc) - a.H[row];
                 reinterpret_cast<T *>(a.Fout)[row] = (T)f;
             } else if (ADJ) {
@@ -1401,7 +1426,7 @@ __global__ void __launch_bounds__(PI_WAVES * WAVE) k_pi_rows(PiArgs a) {
         }
         wave_sync_lds();  // the next item reuses this wave's tile
     }
-    if (REF) return;  // the residual of the recomputed fluid is summed by k_reduce_F
+    if (REF || PROD) return;  // the residual of the recomputed fluid is summed by k_reduce_F
     store_residual_partial(R, mx, red, a.partR + (i64)blockIdx.x * PSR);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
@@ -1474,6 +1499,49 @@ __global__ void k_scaled_by_inv_s(const double *__restrict__ H, const double *__
                                   double *ht) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
         ht[i] = H[i] * inv_s[i];
+}
+
+// out_i = (P v)_i as a left fold over IN row i in ascending source order, each term
+// (w_e / s_j) v_j or (1 / s_j) v_j: the order and rounding of the oracle's product
+__global__ void k_fold_P(const i64 *__restrict__ in_ptr, const int *__restrict__ in_idx, const float *__restrict__ in_w,
+                         const double *__restrict__ inv_s, const double *__restrict__ v, i64 n, double *out) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (i64 p = in_ptr[i]; p < in_ptr[i + 1]; ++p) {
+            const int j = in_idx[p];
+            acc += (in_w ? (double)in_w[p] * inv_s[j] : inv_s[j]) * v[j];
+        }
+        out[i] = acc;
+    }
+}
+
+int launch_P_times(const DevGraph &g, const RowBlocks &rb, const double *v, double *ht, double *out, int ordered,
+                   hipStream_t st) {
+    if (ordered) {
+        k_fold_P<<<grid_for(g.n, 256, 16384), 256, 0, st>>>(g.in_ptr, g.in_idx, g.in_w, g.inv_s, v, g.n, out);
+        DI_LAUNCH_CHECK();
+        return DI_OK;
+    }
+    k_scaled_by_inv_s<<<grid_for(g.n, 256, 16384), 256, 0, st>>>(v, g.inv_s, g.n, ht);
+    DI_LAUNCH_CHECK();
+    PiArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.rb_start = rb.start;
+    a.seg_first = rb.seg_first;
+    a.seg_count = rb.seg_count;
+    a.seg_b = rb.seg_b;
+    a.seg_e = rb.seg_e;
+    a.partial = rb.partial;
+    a.in_ptr = g.in_ptr;
+    a.in_idx = g.in_idx;
+    a.in_w = g.in_w;
+    a.inv_s = g.inv_s;
+    a.n = g.n;
+    a.nrb = rb.nrb;
+    a.nseg = rb.nseg;
+    a.ht = ht;
+    a.Fout = out;
+    return launch_row_pull<PM_PROD>(a, g.weighted, rb, 0, st);
 }
 
 int launch_refine_fluid(const DevGraph &g, const RowBlocks &rb, SolveState &s, const SweepParams &p, double *ht,

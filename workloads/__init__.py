@@ -252,6 +252,47 @@ def from_edges(n: int, src, dst, w=None, name: str = "") -> Graph:
     return Graph(n, out_ptr, dst.astype(np.int32), wv, name)
 
 
+def edit_graph(g: Graph, seed: int, frac: float = 0.01) -> Graph:
+    """An edited copy of g on the same nodes (input for graph updates): a share `frac` of
+    the edges get a new target drawn between their row neighbours' targets (rows stay
+    sorted), frac/2 of the edges are dropped (some sources become dangling), and a tenth
+    of the dangling nodes get one edge to a uniform target.  Edges keep their weights; added
+    edges draw LogNormal(0, 1) weights.  Seeded numpy generator; O(m)."""
+    rng = np.random.default_rng([seed, 0xD1])
+    n, m = g.n, g.m
+    ptr = g.out_ptr
+    idx = g.out_idx.astype(np.int64)
+    w = None if g.w is None else g.w.copy()
+    # moved targets, between the row neighbours' targets
+    mv = np.unique(rng.integers(0, m, size=int(frac * m))) if m else np.zeros(0, np.int64)
+    if len(mv) > 1:  # no two moved edges side by side, so the new targets keep the row order
+        gap = np.diff(mv) > 1
+        mv = mv[np.concatenate([[True], gap]) & np.concatenate([gap, [True]])]
+    row = np.searchsorted(ptr, mv, side="right") - 1
+    lo = np.where(mv > ptr[row], idx[np.maximum(mv - 1, 0)], 0)
+    hi = np.where(mv + 1 < ptr[row + 1], idx[np.minimum(mv + 1, m - 1)], n - 1)
+    idx[mv] = lo + (rng.random(len(mv)) * (hi - lo + 1)).astype(np.int64).clip(0, hi - lo)
+    # dropped edges
+    keep = np.ones(m, dtype=bool)
+    if m:
+        keep[rng.integers(0, m, size=int(frac / 2 * m))] = False
+    drops = np.bincount(np.searchsorted(ptr, np.flatnonzero(~keep), side="right") - 1, minlength=n)
+    # one edge for a tenth of the dangling nodes (their rows are empty, so stay sorted)
+    dang = np.flatnonzero(np.diff(ptr) == 0)
+    add = np.sort(rng.choice(dang, size=len(dang) // 10, replace=False)) if len(dang) >= 10 else dang[:0]
+    add_t = rng.integers(0, n, size=len(add))
+    kept_idx = idx[keep]
+    kept_ptr = np.concatenate([[0], np.cumsum(np.diff(ptr) - drops)])
+    new_idx = np.insert(kept_idx, kept_ptr[add], add_t)
+    deg = np.diff(kept_ptr)
+    deg[add] += 1
+    new_ptr = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    new_w = None
+    if w is not None:
+        new_w = np.insert(w[keep], kept_ptr[add], rng.lognormal(0.0, 1.0, size=len(add)).astype(np.float32))
+    return Graph(n, new_ptr, new_idx.astype(np.int32), new_w, "edit(%s,%g)" % (g.name, frac))
+
+
 # Named configurations of the paper's setting (d = 0.85; uniform Z unless noted).
 def config_graph(name: str) -> Graph:
     if name == "tiny":
