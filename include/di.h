@@ -192,6 +192,24 @@ int di_power(di_ctx *ctx, double tol, di_stats *st);
  */
 int di_adjoint(di_ctx *ctx, const double *g, double tol_inf, double *dZ, double *dw, int on_device, di_stats *st);
 
+/*
+ * di_power without any allocation, for callers that cannot allocate device memory while
+ * it runs (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same power iteration and stop rule as di_power, with the two iterates,
+ * the two x/s vectors and the control block in a static device array of
+ * DI_NOALLOC_SCRATCH_BYTES per device (held until the process ends) instead of
+ * context buffers.  The result goes to x_out, a device array of n doubles (caller's
+ * numbering); di_read(DI_X_PI) is not changed.  Needs n_int * (16 + 2 T) + 256 bytes
+ * (n_int: di_info DI_INFO_N_INTERNAL; T = 4 with float fluid, else 8; each part rounded up
+ * to 256 bytes): up to 1,048,544 nodes with double, 1,398,080 with float x/s.  Larger
+ * graphs: DI_EINVAL.  Always runs in stream mode (no graph capture, no timing events).
+ * Every call on one device shares that device's array: calls that overlap on one device
+ * (several host threads, or several streams) race and must be serialised by the caller.
+ * Single right-hand side, single graph only (DI_EINVAL otherwise).
+ */
+#define DI_NOALLOC_SCRATCH_BYTES (32u << 20)
+int di_power_noalloc(di_ctx *ctx, double tol, double *x_out, di_stats *st);
+
 /* what values for di_read (sizes in elements; k = columns) */
 #define DI_X_RAW 0     /* H (double, n*k, column-major): the raw D-Iteration result */
 #define DI_X_NORM 1    /* (1-d)/(1-d-d l/|Z|_1) H per column: the solution completed by Z/|Z|_1

@@ -25,8 +25,9 @@ INFO_N, INFO_M, INFO_K, INFO_M_LOCAL, INFO_RANGE_LOG2, INFO_INNER_ROUNDS, INFO_F
     INFO_DEVICE_BYTES, INFO_KERNEL_NS, INFO_KERNEL_LAUNCHES, INFO_LOCAL_PUSHES, INFO_REMOTE_UPDATES, INFO_M_REMOTE, \
     INFO_NRANGES, INFO_N_INTERNAL = range(16)
 
-EXPORTED = ["di_init", "di_diffuse", "di_power", "di_adjoint", "di_read", "di_update",
+EXPORTED = ["di_init", "di_diffuse", "di_power", "di_power_noalloc", "di_adjoint", "di_read", "di_update",
             "di_set_sweep", "di_reset", "di_set_z", "di_save", "di_load", "di_info", "di_destroy", "di_last_error"]
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class DIError(RuntimeError):
@@ -79,6 +80,7 @@ def load_library(path: str = LIB_PATH):
     lib.di_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(DiCsr), dbl, vp, ctypes.POINTER(DiOpts)]
     lib.di_diffuse.argtypes = [vp, dbl, ctypes.POINTER(DiStats)]
     lib.di_power.argtypes = [vp, dbl, ctypes.POINTER(DiStats)]
+    lib.di_power_noalloc.argtypes = [vp, dbl, vp, ctypes.POINTER(DiStats)]
     lib.di_adjoint.argtypes = [vp, vp, dbl, vp, vp, ci, ctypes.POINTER(DiStats)]
     lib.di_read.argtypes = [vp, ci, vp, ci]
     lib.di_update.argtypes = [vp, ctypes.POINTER(DiCsr)]
@@ -187,6 +189,15 @@ class Solver:
     def power(self, tol: float) -> dict:
         st = DiStats()
         _check(self._lib.di_power(self._ctx, float(tol), ctypes.byref(st)))
+        return st.as_dict()
+
+    def power_noalloc(self, tol: float, x_out) -> dict:
+        """Power iteration into x_out (a device tensor of n doubles) with no allocation
+        in the library: its vectors live in the library's per-device scratch array."""
+        if not (_is_torch(x_out) and x_out.is_cuda and x_out.is_contiguous()):
+            raise ValueError("x_out must be a contiguous device tensor")
+        st = DiStats()
+        _check(self._lib.di_power_noalloc(self._ctx, float(tol), ctypes.c_void_p(x_out.data_ptr()), ctypes.byref(st)))
         return st.as_dict()
 
     def adjoint(self, g, tol_inf: float, want_dw: bool = True):

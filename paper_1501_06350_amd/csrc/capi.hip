@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 #include <numeric>
 
@@ -88,9 +89,38 @@ struct di_ctx {
     i64 kernel_launches = 0;
     // mass balance per column / graph after the last di_diffuse
     std::vector<double> defects;
+    // this device's copy of the no-allocation scratch (see di_power_noalloc)
+    unsigned char *scratch = nullptr;
 };
 
+// Scratch memory of di_power_noalloc: the power iteration's two iterates (double), its two
+// x/s vectors (fluid type) and its control block, each at a 256-byte boundary.  Every
+// device holds its own copy for the life of the process.  In host code the array's name is
+// not a device address: host code uses the address hipGetSymbolAddress returned for the
+// current device (noalloc_scratch), never the name.
+static __device__ __align__(256) unsigned char scratch[DI_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's copy of the scratch array (looked up once per device).
+int noalloc_scratch(unsigned char **out) {
+    int dev = 0;
+    DI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) DI_FAIL(DI_EINVAL, "device %d beyond the %d the library supports", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) DI_FAIL(DI_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return DI_OK;
+}
 
 template <typename T>
 int dalloc(di_ctx *c, T **p, i64 count) {
@@ -865,6 +895,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         return code;
     };
     if ((rc = set_kernel_attributes()) != DI_OK) return fail(rc);
+    if ((rc = noalloc_scratch(&c->scratch)) != DI_OK) return fail(rc);
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         set_error("hipEventCreate failed");
         return fail(DI_EHIP);
@@ -1027,7 +1058,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         c->s.rb = rb;
     }
     // one graph: the IN row blocks of power iteration (and of the float fluid's
-    // recomputation and the graph update) are built here
+    // recomputation) are built here, so that di_power_noalloc needs no allocation
     if (c->n_graphs == 1 && (rc = ensure_row_blocks(c)) != DI_OK) return fail(rc);
     if ((rc = reset_state(c)) != DI_OK) return fail(rc);
     *out = c;
@@ -1292,6 +1323,63 @@ int di_power(di_ctx *c, double tol, di_stats *st) {
     fill_stats(st, h, before, c->d, c->p.K, ms, true);
     if (h.overflow) DI_FAIL(DI_ENUMERIC, "non-finite value in the power-iteration residual");
     c->pi_done = true;  // X_PI holds the last iterate (also after DI_ENOCONV)
+    if (!h.done) DI_FAIL(DI_ENOCONV, "iteration budget spent before the tolerance");
+    return DI_OK;
+}
+
+int di_power_noalloc(di_ctx *c, double tol, double *x_out, di_stats *st) {
+    if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
+    if (!x_out) DI_FAIL(DI_EINVAL, "x_out is NULL");
+    if (!(tol > 0.0) || !std::isfinite(tol)) DI_FAIL(DI_EINVAL, "tol must be finite and > 0");
+    if (c->k != 1 || c->n_graphs != 1) DI_FAIL(DI_EINVAL, "di_power_noalloc supports one right-hand side on one graph");
+    if (!c->rbin_ready || !c->scratch) DI_FAIL(DI_ESTATE, "the context has no row blocks or scratch");
+    const i64 n = c->g.n;
+    const size_t T = c->p.fp32 ? 4 : 8;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t bx = up((size_t)n * 8), bt = up((size_t)n * T), need = 2 * bx + 2 * bt + up(sizeof(DevCtl));
+    if (need > (size_t)DI_NOALLOC_SCRATCH_BYTES)
+        DI_FAIL(DI_EINVAL, "n = %lld (internal) needs %zu bytes of scratch, more than the %zu of di_power_noalloc",
+                (long long)n, need, (size_t)DI_NOALLOC_SCRATCH_BYTES);
+    // the context's state with the iterates, x/s vectors and control block in the scratch
+    SolveState s = c->s;
+    unsigned char *p = c->scratch;
+    s.X[0] = reinterpret_cast<double *>(p);
+    s.X[1] = reinterpret_cast<double *>(p + bx);
+    s.XT[0] = p + 2 * bx;
+    s.XT[1] = p + 2 * bx + bt;
+    s.pctl = reinterpret_cast<DevCtl *>(p + 2 * bx + 2 * bt);
+    c->p.tol = tol;
+    // every buffer starts from zero (the scratch keeps the last call's contents); fill
+    // kernels, no memset nodes
+    DI_TRY(launch_pi_init(c->g, s, c->p, c->st));
+    DI_TRY(launch_fill_zero(s.pctl, sizeof(DevCtl), c->st));
+    k_ctl_begin<<<1, 1, 0, c->st>>>(s.pctl, (long long)c->o.max_sweeps);
+    DI_LAUNCH_CHECK();
+    DI_TRY(sync_ctl(c, s.pctl));
+    const DevCtl before = *c->h_ctl;
+    DI_HIP(hipEventRecord(c->ev0, c->st));
+    while (true) {  // stream mode always (a captured graph would allocate)
+        for (int k = 0; k < c->spc; ++k) DI_TRY(enqueue_pi_iteration_on(c, s, c->st));
+        DI_TRY(sync_ctl(c, s.pctl));
+        const DevCtl &h = *c->h_ctl;
+        if (h.done || h.overflow || h.sweep >= h.budget) break;
+    }
+    const double *xr = s.X[c->h_ctl->parity];
+    if (c->seg) {
+        k_seg_to_caller<<<grid_for(n, 256, 16384), 256, 0, c->st>>>(xr, x_out, c->d_seg_start, c->seg_rb, n);
+        DI_LAUNCH_CHECK();
+    } else {
+        DI_HIP(hipMemcpyAsync(x_out, xr, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
+    }
+    DI_HIP(hipEventRecord(c->ev1, c->st));
+    DI_TRY(sync_ctl(c, s.pctl));
+    float ms = 0.0f;
+    DI_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    DevCtl h = *c->h_ctl;
+    h.tot_edges = (u64)(h.sweep * c->g.m);
+    h.tot_nodes = (u64)(h.sweep * n);
+    fill_stats(st, h, before, c->d, c->p.K, ms, true);
+    if (h.overflow) DI_FAIL(DI_ENUMERIC, "non-finite value in the power-iteration residual");
     if (!h.done) DI_FAIL(DI_ENOCONV, "iteration budget spent before the tolerance");
     return DI_OK;
 }
