@@ -77,6 +77,11 @@ struct di_ctx {
     double *aF = nullptr;
     double *asnap = nullptr;
     DevCtl *actl = nullptr;
+    // fast adjoint: the transposed graph on the forward graph's ranges, and its two
+    // in-flight buffers (values, then the bitmap of the nonzero ones)
+    DevGraph gT;
+    bool gT_ready = false;
+    void *aS[2] = {nullptr, nullptr};
     // batched / multi-graph solve (k > 1 or n_graphs > 1)
     BatchState *b = nullptr;
     // captured sweep chunk (loop_mode = DI_LOOP_GRAPH)
@@ -705,12 +710,13 @@ int di_destroy(di_ctx *c) {
     if (!c) return DI_OK;
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     free_graph(c->g);
+    free_graph(c->gT);
     free_row_blocks(c->rbin);
     free_row_blocks(c->rbout);
     void *ps[] = {c->s.F, c->s.F0, c->s.H, c->s.S[0], c->s.S[1], c->s.snap, c->s.frontier, c->s.range_order,
                   c->s.ctl, c->s.X[0], c->s.X[1], c->s.XT[0], c->s.XT[1], c->s.pctl, c->s.Z, c->lam,
                   c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.range_cnt, c->d_seg_start, c->s.ginfo, c->s.gctl,
-                  c->d_gp, c->d_gs, c->d_gscale, c->ref_ht, c->s.partH, c->s.hsum};
+                  c->d_gp, c->d_gs, c->d_gscale, c->ref_ht, c->s.partH, c->s.hsum, c->aS[0], c->aS[1]};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     if (c->b) free_batch(c->b);
@@ -1682,25 +1688,76 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ_INIT, c->st, c->s.partR, anR, c->s.partC, 0));
     DI_TRY(sync_ctl(c, c->actl));
     DevCtl before = *c->h_ctl;
-    // deterministic contexts: snapshot and a row-order pull (reproducible, the oracle's
-    // order); otherwise the same snapshot and a wave-per-row-block pull
-    if (!c->o.deterministic && !c->rbout_ready) {
-        DI_TRY(build_row_blocks(c->rbout, c->g.out_ptr, n, c->st));
-        c->rbout_ready = true;
-    }
-    while (!c->h_ctl->done) {
-        for (int k = 0; k < c->spc; ++k) {
-            if (c->o.deterministic)
+    if (c->o.deterministic) {
+        // snapshot and a row-order pull over OUT: reproducible, the oracle's order
+        while (!c->h_ctl->done) {
+            for (int k = 0; k < c->spc; ++k) {
                 DI_TRY(launch_adj_sweep(c->g, c->aF, c->lam, c->asnap, c->actl, ap, c->st, c->s.partR, c->s.partC,
                                         &anR, &anC));
-            else
-                DI_TRY(launch_adj_sweep_fast(c->g, c->rbout, c->aF, c->lam, c->asnap, c->actl, ap, c->st, c->s.partR,
-                                             c->s.partC, &anR, &anC));
-            DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ, c->st, c->s.partR, anR, c->s.partC, anC));
+                DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ, c->st, c->s.partR, anR, c->s.partC, anC));
+            }
+            DI_TRY(sync_ctl(c, c->actl));
+            const DevCtl &h = *c->h_ctl;
+            if (h.done || h.overflow || h.sweep >= h.budget) break;
         }
-        DI_TRY(sync_ctl(c, c->actl));
-        const DevCtl &h = *c->h_ctl;
-        if (h.done || h.overflow || h.sweep >= h.budget) break;
+    } else {
+        // block-local sweeps on the transposed graph (same ranges and numbering): a node
+        // pushes its fluid along its IN row, local targets in LDS, the rest in flight to the
+        // next sweep.  The stop needs max |F| with nothing in flight: when a sweep's
+        // partials (max |F| as the sweep began, in-flight fluid delivered) meet the
+        // tolerance, a delivery-only pass measures the state the call returns.
+        if (!c->gT_ready) {
+            c->gT.n = n;
+            c->gT.m = c->g.m;
+            c->gT.weighted = c->g.weighted;
+            const int brc = build_graph(c->gT, c->g.in_ptr, c->g.in_idx, c->g.in_w, c->g.rb, true, c->st);
+            if (brc != DI_OK) {
+                free_graph(c->gT);
+                return brc;
+            }
+        }
+        // in-flight buffers of double fluid (whatever the forward fluid type): n values,
+        // then the bitmap of the nonzero ones
+        const i64 s_vals = ((i64)(n * 8) + 255) & ~(i64)255;
+        const i64 s_bytes = s_vals + ((n + 63) / 64) * 8;
+        if (!c->aS[0]) {
+            DI_TRY(dalloc(c, (char **)&c->aS[0], s_bytes));
+            DI_TRY(dalloc(c, (char **)&c->aS[1], s_bytes));
+        }
+        c->gT_ready = true;
+        SolveState as;
+        as.F = c->aF;
+        as.H = c->lam;
+        as.S[0] = c->aS[0];
+        as.S[1] = c->aS[1];
+        as.Sb[0] = reinterpret_cast<u64 *>(static_cast<char *>(c->aS[0]) + s_vals);
+        as.Sb[1] = reinterpret_cast<u64 *>(static_cast<char *>(c->aS[1]) + s_vals);
+        as.S_bytes = s_bytes;
+        as.ctl = c->actl;
+        as.range_order = c->s.range_order;
+        as.range_cnt = c->s.range_cnt;
+        as.partR = c->s.partR;
+        as.partC = c->s.partC;
+        DI_TRY(launch_fill_zero(as.S[0], as.S_bytes, c->st));
+        DI_TRY(launch_fill_zero(as.S[1], as.S_bytes, c->st));
+        while (!c->h_ctl->done) {
+            for (int k = 0; k < c->spc; ++k) {
+                DI_TRY(launch_adj_bld_sweep(c->gT, c->g.inv_s, as, ap, c->rounds, c->st));
+                DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ, c->st, as.partR, as.nR, as.partC, as.nC));
+            }
+            DI_TRY(sync_ctl(c, c->actl));
+            if (c->h_ctl->overflow) break;
+            if (c->h_ctl->done) {
+                DI_TRY(launch_adj_bld_sweep(c->gT, c->g.inv_s, as, ap, 0, c->st));
+                DI_TRY(launch_finalize(c->actl, ap, FIN_DELIVER, c->st, as.partR, as.nR, as.partC, as.nC));
+                DI_TRY(sync_ctl(c, c->actl));
+                if (c->h_ctl->maxF / (1.0 - c->d) <= tol_inf) break;
+                k_ctl_reopen<<<1, 1, 0, c->st>>>(c->actl);  // not yet: more sweeps
+                DI_LAUNCH_CHECK();
+                DI_TRY(sync_ctl(c, c->actl));
+            }
+            if (c->h_ctl->sweep >= c->h_ctl->budget) break;
+        }
     }
     // gradients from x = H (forward history) and lambda
     // (dZ goes through an internal-layout buffer for host outputs and cut-aligned ranges;

@@ -156,6 +156,12 @@ int launch_adj_sweep_fast(const DevGraph &g, const RowBlocks &rb_out, double *F,
 // (else one sum) on 2^-K into out[0 .. n_graphs); part: max(nranges, PART_MIN) * PSR words
 int launch_node_sums(const DevGraph &g, SolveState &s, const void *v, int is_float, int K, u64 *part, double *out,
                      hipStream_t st);
+// Fast adjoint sweep: the block-local sweep on the transposed graph gT (ranges and
+// numbering of the forward graph), fluid in as.F, history in as.H, in-flight buffers in
+// as.S / as.Sb, control block as.ctl; tinv = 1/s of the forward graph.  The partial slots
+// carry max |F| right after the fluid in flight arrived (rounds == 0: delivery only).
+int launch_adj_bld_sweep(const DevGraph &gT, const double *tinv, SolveState &as, const SweepParams &p, int rounds,
+                         hipStream_t st);
 int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR);
 int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
                      hipStream_t st);

@@ -90,6 +90,9 @@ struct BldArgs {
     const double *inv_s;
     const double *rw;
     const int *range_order;
+    // adjoint sweeps on the transposed graph: 1/s_j of the forward graph at each target j
+    // (the push from i to j carries P[i][j] = w(j->i) / s_j); nullptr otherwise
+    const double *tinv;
     i64 n;
     int rb;
     void *F;
@@ -119,7 +122,12 @@ __device__ __forceinline__ bool range_schedule(const int *range_graph, const Gra
     return true;
 }
 
-template <typename T, bool WTD>
+// ADJ: the adjoint diffusion (lambda = (I - d P^T)^{-1} g) on the transposed graph: the
+// push from i along its transposed edge to j carries d f w_e / s_j (s_j of the forward
+// graph, a.tinv), so the factor is applied at the target; the fluid is signed; the
+// partial slot's maximum is max |F| of the range right after the fluid in flight arrived
+// (the exact state between two sweeps), which the L-infinity stop needs.
+template <typename T, bool WTD, bool ADJ = false>
 __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     DevCtl *ctl = a.ctl;
@@ -188,6 +196,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
                 if (pb + (i64)u * BLD_THREADS < p1 && v[u] != (T)0) {
                     T add = v[u];
                     if (WTD) add = (T)((double)add * (double)wv[u]);
+                    if (ADJ) add = (T)((double)add * a.tinv[base + tg[u]]);
                     atomicAdd(&Fl[tg[u]], add);
                     ++delivered;
                 }
@@ -195,6 +204,12 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
         }
     }
     __syncthreads();
+    u64 mstart = 0;  // adjoint: max |F| of the range with the fluid in flight delivered
+    if (ADJ)
+        for (int i = threadIdx.x; i < cnt; i += BLD_THREADS) {
+            const u64 b = (u64)__double_as_longlong(fabs((double)Fl[i]));
+            mstart = b > mstart ? b : mstart;
+        }
 
     // 2. local rounds; wave w owns [my0, my1)
     const int sub = (((cnt + BLD_WAVES - 1) / BLD_WAVES) + WAVE - 1) & ~(WAVE - 1);
@@ -223,7 +238,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
                 if (inv == 0.0) {
                     if (!limbs_add_signed_checked(leak, f, a.K)) bad = 1;
                 } else {
-                    q = (a.d * f) * inv;
+                    q = ADJ ? a.d * f : (a.d * f) * inv;
                     if (a.rw[gi] > 0.0) Sl[i] = (T)((double)Sl[i] + q);
                     st = a.loc_ptr[gi];
                     dg = (int)(a.loc_ptr[gi + 1] - st);
@@ -258,6 +273,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
                     const i64 p = sc_start[lo] + (s - sc_off[lo]);
                     tgt[u] = a.loc_tgt[p];
                     val[u] = WTD ? sc_q[lo] * (double)a.loc_w[p] : sc_q[lo];
+                    if (ADJ) val[u] *= a.tinv[base + tgt[u]];
                 }
 #pragma unroll
                 for (int u = 0; u < EDGE_U; ++u)
@@ -281,15 +297,16 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
         if (s != (T)0) Snext[base + i] = s;
         if ((threadIdx.x & (WAVE - 1)) == 0) Sbnext[(base + i) >> 6] = bits;
         if (!limbs_add_checked(R, fabs((double)v), a.K)) bad = 1;
-        if (s != (T)0 && !limbs_add_checked(R, fabs((double)s) * a.rw[base + i], a.K)) bad = 1;
+        if (!ADJ && s != (T)0 && !limbs_add_checked(R, fabs((double)s) * a.rw[base + i], a.K)) bad = 1;
     }
-    store_residual_partial(R, 0, red, a.partR + (i64)r * PSR);
+    store_residual_partial(R, mstart, red, a.partR + (i64)r * PSR);
     store_counter_partial(leak, nodes, edges + delivered, delivered, red, a.partC + (i64)r * PSC);
     if (threadIdx.x == 0 && bad) atomicOr(&ctl->overflow, 1);
 }
 
 static BldArgs make_bld_args(const DevGraph &g, SolveState &s, const SweepParams &p, int rounds) {
     BldArgs a;
+    a.tinv = nullptr;
     a.loc_ptr = g.loc_ptr;
     a.loc_tgt = g.loc_tgt;
     a.loc_w = g.loc_w;
@@ -782,6 +799,19 @@ int launch_bld_sweep(const DevGraph &g, SolveState &s, const SweepParams &p, int
         if (g.weighted) k_bld_sweep<double, true><<<grid, BLD_THREADS, lds, st>>>(a);
         else k_bld_sweep<double, false><<<grid, BLD_THREADS, lds, st>>>(a);
     }
+    DI_LAUNCH_CHECK();
+    return DI_OK;
+}
+
+int launch_adj_bld_sweep(const DevGraph &gT, const double *tinv, SolveState &as, const SweepParams &p, int rounds,
+                         hipStream_t st) {
+    BldArgs a = make_bld_args(gT, as, p, rounds);
+    a.tinv = tinv;
+    as.nR = as.nC = gT.nranges;
+    const size_t lds = bld_lds_bytes(gT.rb, 0);
+    const unsigned grid = (unsigned)gT.nranges;
+    if (gT.weighted) k_bld_sweep<double, true, true><<<grid, BLD_THREADS, lds, st>>>(a);
+    else k_bld_sweep<double, false, true><<<grid, BLD_THREADS, lds, st>>>(a);
     DI_LAUNCH_CHECK();
     return DI_OK;
 }
@@ -1694,6 +1724,8 @@ int set_kernel_attributes() {
     DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
     DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
     DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
+    DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<double, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
+    DI_HIP(hipFuncSetAttribute((const void *)k_bld_sweep<double, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
     DI_HIP(hipFuncSetAttribute((const void *)k_bld2_sweep<float>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
     DI_HIP(hipFuncSetAttribute((const void *)k_bld2_sweep<double>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb));
     done = true;

@@ -73,6 +73,32 @@ def test_adjoint_vs_dense_and_fast_forward(gpu):
             assert np.abs(dw - dw_ref).max() <= rel * np.abs(dw_ref).max()
 
 
+@pytest.mark.parametrize("name", ["web50k", "web50k_w", "tiny20k"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_fast_adjoint_against_oracle(gpu, name, fp32):
+    """The block-local adjoint on the transposed graph (cut-aligned ranges, signed fluid)
+    against the oracle's adjoint run to a tight L-infinity bound, and its own certificate;
+    two calls in a row on one context."""
+    g = {"web50k": lambda: W.webgen(50_000, 12), "web50k_w": lambda: W.webgen(50_000, 13, weighted=True),
+         "tiny20k": lambda: W.tiny_zipf(20_000, 4)}[name]()
+    say("fast adjoint", name, "fp32", fp32)
+    og = O.OGraph.of(g)
+    lam_o, _, _, conv = O.adjoint(og, D, W.normal_vector(g.n, 9), tol_inf=1e-14)
+    assert conv
+    lam_o2, _, _, _ = O.adjoint(og, D, W.normal_vector(g.n, 10), tol_inf=1e-14)
+    with gpu.from_graph(g, d=D, fluid_fp32=fp32) as s:
+        s.diffuse(1e-11)
+        for c, lo in ((W.normal_vector(g.n, 9), lam_o), (W.normal_vector(g.n, 10), lam_o2)):
+            dZ, dw, st = s.adjoint(c, 1e-11)
+            assert st["converged"] and st["bound"] <= 1e-11
+            lam = s.read(gpu.LAMBDA)
+            err = np.abs(lam - lo).max()
+            say("  %d sweeps, bound %.3e, |lambda - oracle|_inf %.3e" % (st["sweeps"], st["bound"], err))
+            assert err <= st["bound"] + 2e-14
+            assert err <= 1e-9 * np.abs(lo).max()
+            np.testing.assert_allclose(dZ, (1 - D) * lam, rtol=1e-15, atol=0)
+
+
 def test_duality_and_sampled_rows_at_scale(gpu):
     """Config of the adjoint workload: web-like graph, n = 2M, LogNormal(0,1) weights."""
     g = W.webgen(2_000_000, 5, weighted=True)
