@@ -395,8 +395,8 @@ def _timed(fn):
 
 def bench_batched(fp32):
     """Personalized PageRank, webgen(4M, seed 4), k=64 columns of 16 seeds each, L1 tol 1e-8
-    per column: one k=64 tile solve (float fluid, the tile's precision, theta 1 with 4 rounds:
-    its best) vs 64 single-column solves on the same resident graph (di_set_z between them,
+    per column: one k=64 tile solve (float fluid, the tile's precision, theta and rounds from
+    the autotuner) vs 64 single-column solves on the same resident graph (di_set_z between them,
     outside the timed calls) in float and double fluid with (theta, rounds) = (1, 4), (0.5, 4)
     and (0.2, 6); the speedup is taken against the fastest of the six."""
     import numpy as np
@@ -424,7 +424,12 @@ def bench_batched(fp32):
     best_key = min(singles, key=lambda q: singles[q][0])
     best = singles[best_key][0]
     out["best_single"] = best_key
-    with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=fp32) as sb:
+    # the tile's theta and local rounds from the autotuner (outside the timed solve)
+    from paper_1501_06350_amd import tune
+    t0 = time.time()
+    tt = tune.Tuner(None, log=log).tune_tile(g, Z, D, TOL, fluid_fp32=fp32)
+    out["tile_autotuner"] = dict(tt, seconds=round(time.time() - t0, 1))
+    with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=fp32, theta=tt["theta"], inner_rounds=tt["inner_rounds"]) as sb:
         sb.diffuse(TOL)  # warm-up
         sb.reset()
         st, ms = _timed(lambda: sb.diffuse(TOL))

@@ -380,3 +380,34 @@ def test_set_z_matches_fresh_context(gpu, kind):
         with pytest.raises(gpu.DIError):
             s.set_z(-np.ones_like(Z2))
         np.testing.assert_array_equal(s.read(gpu.H), ref)  # a rejected Z changes nothing
+
+
+@pytest.mark.parametrize("kind", ["tile", "union"])
+def test_graph_loop_mode_fast_batched(gpu, kind):
+    """The fast tile (float fluid) and the fast union of graphs under HIP-graph capture:
+    replays with eager work between them meet every column's / graph's certificate."""
+    if kind == "tile":
+        g = W.webgen(20_000, 3)
+        Z = W.ppr_Z(g.n, 8, 16, seed=2)
+        og = O.OGraph.of(g)
+        refs = [exact(og, Z[:, c]) for c in range(8)]
+        make = lambda lm: gpu.from_graph(g, d=D, Z=Z, k=8, fluid_fp32=True, loop_mode=lm, sweeps_per_sync=3)
+    else:
+        graphs = small_union()
+        g, gp = W.union(graphs)
+        refs = [exact(O.OGraph.of(q), np.full(q.n, 1.0 / q.n)) for q in graphs]
+        make = lambda lm: gpu.Solver(g.n, g.out_ptr, g.out_idx, None, d=D, graph_ptr=gp, loop_mode=lm,
+                                     sweeps_per_sync=3)
+    for lm in (gpu.LOOP_STREAM, gpu.LOOP_GRAPH):
+        say("fast", kind, "loop mode", lm)
+        with make(lm) as s:
+            for rep in range(3):
+                s.reset()
+                st = s.diffuse(1e-9)
+                assert st["converged"], (lm, rep)
+                H = s.read(gpu.H)
+                R = s.read(gpu.RESIDUALS)
+                for q, xr in enumerate(refs):
+                    h = H[q] if kind == "tile" else H[gp[q]:gp[q + 1]]
+                    assert np.abs(h - xr).sum() <= R[q] / (1 - D) * (1 + 1e-6) + 1e-13, (lm, rep, q)
+                s.read(gpu.X_NORM)  # eager work between replays

@@ -326,3 +326,30 @@ def test_graph_loop_mode_matches_stream(gpu):
     assert res[0][0] == res[2][0]
     np.testing.assert_array_equal(res[0][1], res[2][1])
     np.testing.assert_array_equal(res[1][1], res[3][1])
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_graph_loop_mode_fast_sweeps(gpu, oracle_graphs, fp32):
+    """Fast block-local sweeps (and the float fluid's recomputation) under HIP-graph
+    capture: every replay of the captured chunk, with eager work and synchronisation
+    between replays, meets the certificate against the oracle; the sweep count stays near
+    the stream-mode one (fast sweeps are not reproducible bit for bit)."""
+    g, og = GRAPHS["web20k"], oracle_graphs["web20k"]
+    Z = O.uniform_Z(g.n)
+    x = reference_x(og, Z)
+    rel = 1e-6 if fp32 else 1e-9
+    sweeps = {}
+    for lm in (gpu.LOOP_STREAM, gpu.LOOP_GRAPH):
+        say("fast sweeps, loop mode", lm, "fp32", fp32)
+        with gpu.from_graph(g, d=D, fluid_fp32=fp32, loop_mode=lm, sweeps_per_sync=4) as s:
+            for rep in range(3):
+                s.reset()
+                st = s.diffuse(1e-11)
+                H = s.read(gpu.H)
+                assert st["converged"], (lm, rep)
+                err = np.abs(H - x).sum()
+                assert err <= st["bound"] * (1 + 1e-6) + 1e-14, (lm, rep, err, st["bound"])
+                assert err <= rel * np.abs(x).sum()
+                s.power(1e-11)  # eager work between replays
+            sweeps[lm] = st["sweeps"]
+    assert abs(sweeps[gpu.LOOP_STREAM] - sweeps[gpu.LOOP_GRAPH]) <= 3
