@@ -70,14 +70,18 @@ typedef struct {
  *   max_sweeps     : sweep (or iteration) budget per di_diffuse / di_power call [100000]
  *   deterministic  : 1 = synchronous sweeps with snapshot semantics and ordered
  *                    accumulation (bit-reproducible, slower) [0]
- *   range_log2     : block-local range size 2^range_log2 nodes, 8..16 (0 = auto)
+ *   range_log2     : block-local range size 2^range_log2 nodes, 8..14 (f32 fluid) or
+ *                    8..13 (0 = auto).  With k > 1: 6..9 runs the tile's block-local
+ *                    sweep (auto: the largest range whose fluid tile lets two
+ *                    workgroups share a compute unit), larger sizes its plain push sweep
  *   inner_rounds   : block-local diffusion rounds per sweep, 1..64 (0 = auto)
  *   k              : number of right-hand sides (columns of Z), 1..64 [1].  k > 1
  *                    diffuses an n x k fluid tile (personalized PageRank, Section 2.1):
  *                    a node is taken when any column's fluid reaches that column's
  *                    threshold, and then every column of the row is diffused; each
- *                    column has its own residual and stop.  Block-local options do not
- *                    apply; di_power, di_adjoint and checkpoints are single-column only.
+ *                    column has its own residual and stop.  theta and inner_rounds
+ *                    apply to the tile's sweeps, range_cut does not; di_power,
+ *                    di_adjoint and checkpoints are single-column only.
  *   n_graphs       : > 1 declares the graph a block-diagonal union of independent
  *                    graphs whose node ranges are given by graph_ptr [1].  Every edge
  *                    must stay inside its graph.  Each graph g is solved as its own

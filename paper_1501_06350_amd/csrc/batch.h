@@ -13,7 +13,7 @@ int init_batch(BatchState *&b, const DevGraph &g, SweepParams &p, int k, int det
                const int *range_order, int rounds, hipStream_t st);
 // range size (log2) whose fluid and history-increment tiles fit in LDS for k columns
 // (0 if none does: the fast sweep then uses global atomics)
-int tile_range_log2(int k, int fp32);
+int tile_range_log2(int k, int fp32, int weighted);
 int reset_batch(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st);
 // new right-hand sides (validated by the caller; NULL = uniform), then reset
 int set_batch_z(BatchState *b, const DevGraph &g, SweepParams &p, const double *Z, hipStream_t st);

@@ -79,7 +79,7 @@ struct BatchState {
     // block-local sweeps
     int bld = 0, rounds = 4, gridB = 0, gridD = 0;
     void *S = nullptr;           // in-flight rows (n x k)
-    unsigned char *fl = nullptr; // n: the row of S is nonzero
+    unsigned *fl = nullptr;      // (n + 31) / 32 words: bit i, row i of S holds this sweep's fluid
     int *blk_ptr = nullptr;      // gridB + 1: each workgroup's share of blk_ranges
     int *blk_ranges = nullptr;   // nranges: ranges grouped by workgroup
     DlUnit *units = nullptr;     // delivery units over the cross-range in-entries
@@ -139,6 +139,27 @@ __device__ __forceinline__ void block_columns_store(u64 (&v)[NV], u64 *lds, u64 
         for (int q = 0; q < NV; ++q) {
             u64 s = 0;
             for (int x = 0; x < NW; ++x) {
+                const u64 y = lds[(x * WAVE + lane) * NV + q];
+                s = ((MAXMASK >> q) & 1u) ? (y > s ? y : s) : s + y;
+            }
+            out[lane * NV + q] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// block_columns_store over nw waves (a runtime count); lds: u64[nw * 64 * NV]
+template <int NV, unsigned MAXMASK = 0>
+__device__ __forceinline__ void block_columns_store_n(u64 (&v)[NV], u64 *lds, u64 *out, int k, int nw) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lds[(w * WAVE + lane) * NV + q] = v[q];
+    __syncthreads();
+    if (w == 0 && lane < k) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            u64 s = 0;
+            for (int x = 0; x < nw; ++x) {
                 const u64 y = lds[(x * WAVE + lane) * NV + q];
                 s = ((MAXMASK >> q) & 1u) ? (y > s ? y : s) : s + y;
             }
@@ -246,16 +267,20 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
 // ---------------------------------------------------------------------------
 // Block-local fast sweep of the tile, in two kernels per sweep.
 //
-// k_tile_bld: node ids are grouped into ranges of 2^rb rows; a workgroup takes its
-// ranges one after another and keeps a range's fluid tile F[B][k] (fluid type) and the
-// sweep's history increments dH[B][k] (double for every fluid type) in LDS.  For a range it
-//   1. stages the fluid rows (they already hold what other ranges sent last sweep);
-//   2. runs up to `rounds` local rounds: each wave scans its share of rows, takes a row
-//      when some running column reaches its threshold (every running column of the row
-//      is diffused, Section 3.1), adds it to dH and pushes d f P e_i along the row's
-//      local edges with LDS atomics (one k-lane row add per edge);
-//   3. writes F back, adds dH to H, and for rows with cross-range edges writes the
-//      in-flight row S_i = d dH_i / s_i and a flag telling whether it is nonzero.
+// k_tile_bld: node ids are grouped into ranges of B = 2^rb rows; a workgroup of B / 32
+// waves takes its ranges one after another, wave w owning rows [32 w, 32 w + 32) of a
+// range.  The range's fluid tile F[B][k] (fluid type) and its local edge lists sit in
+// LDS; lane c of a wave holds column c.  For a range it
+//   1. stages the fluid rows (they already hold what other ranges sent last sweep) and
+//      the targets (and weights) of the range's local edges;
+//   2. runs up to `rounds` local rounds: each wave scans its rows, takes a row when some
+//      running column reaches its threshold (every running column of the row is
+//      diffused, Section 3.1), adds it to the row of H (an atomic add in this XCD's L2:
+//      no other wave touches the row during the sweep), pushes d f P e_i along the
+//      row's local edges with LDS atomics (one k-lane row add per edge) and, for a row
+//      with cross-range edges, adds d f / s_i to the row's in-flight fluid S_i;
+//   3. writes its rows of F back and flags the rows whose S_i holds this sweep's fluid
+//      (one bit per row).
 // k_tile_deliver: one wave per unit of cross-range in-entries (whole target rows,
 //   or a segment of a long row) gathers the flagged in-flight rows, adds them up per
 //   target in registers and adds the sum to the target's fluid row.
@@ -263,13 +288,17 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
 // the per-XCD L2 caches.  The residual of every column, |F|_1 plus the fluid in
 // flight, is summed at write-back; delivery moves fluid without changing it.
 // ---------------------------------------------------------------------------
-// Two workgroups of 8 waves share a compute unit, so that one stages or writes back a
-// range while the other runs local rounds: the range size is the largest whose tiles
-// fit in half of the 160 KB of LDS.
-constexpr int TB_THREADS = 512;
-constexpr int TB_WAVES = TB_THREADS / WAVE;
+// Ranges of up to 2^8 rows run two workgroups per compute unit (one stages or writes
+// back a range while the other runs local rounds), each within TB_LDS of LDS; 2^9-row
+// ranges run one workgroup of 16 waves per compute unit with up to TB_LDS_ONE.
+constexpr int TB_RPW = 32;  // rows per wave (at most 32: one bit each in a wave-uniform mask)
+constexpr int TB_MAXW = 16; // waves per workgroup at 2^9-row ranges
+static_assert(TB_RPW == 32 && (1 << 6) % TB_RPW == 0, "a wave's rows are one 32-bit word of flags");
+constexpr int TB_MAX_THREADS = TB_MAXW * WAVE;
 constexpr int TB_GRID = 1024;
-constexpr size_t TB_LDS = 78 * 1024;  // fluid tile + dH tile + degrees + local row offsets
+constexpr size_t TB_LDS = 78 * 1024;
+constexpr size_t TB_LDS_ONE = 156 * 1024;
+constexpr int TB_MIN_RB = 6, TB_MAX_RB = 9;
 constexpr int DL_THREADS = 256;
 constexpr int DL_WAVES = DL_THREADS / WAVE;
 constexpr int DL_GRID = 4096;
@@ -286,47 +315,138 @@ struct TileBldArgs {
     const int *blk_ptr, *blk_ranges;
     i64 n, nranges;
     int rb, k, K, rounds;
+    int le_max;  // local edges of a range that fit the LDS edge buffer
     void *F;
     double *H;
     void *S;
-    unsigned char *fl;
+    unsigned *fl;
     TileCtl *ctl;
     double d;
     u64 *partR, *partC, *partK;
 };
 
-__host__ __device__ inline size_t tile_bld_lds(int rb, int k, int tsize) {
+inline size_t tile_edge_bytes(bool weighted) { return weighted ? 6 : 2; }
+
+// LDS of a range (the edge buffer comes on top): the fluid tile, degrees and local row
+// offsets (u32), then per row the out-weight of its cross-range edges and, for weighted
+// graphs, 1/s_i (doubles, 8-byte aligned)
+__host__ __device__ inline size_t tile_rowdata_offset(int rb, int k, int tsize) {
     const size_t B = (size_t)1 << rb;
-    return B * k * tsize + B * k * 8 + B * 4 + (B + 1) * 4;
+    return (B * k * tsize + (2 * B + 1) * 4 + 7) & ~(size_t)7;
 }
 
-// dynamic LDS of a launch: the tiles, and at least the per-column reduction scratch
-// that reuses them at the end
-inline size_t tile_bld_lds_launch(int rb, int k, int tsize) {
-    return std::max(tile_bld_lds(rb, k, tsize), (size_t)TB_WAVES * WAVE * PSR * sizeof(u64));
+__host__ __device__ inline size_t tile_bld_fixed_lds(int rb, int k, int tsize, bool weighted) {
+    const size_t B = (size_t)1 << rb;
+    return tile_rowdata_offset(rb, k, tsize) + B * 8 * (weighted ? 2 : 1) + 16;
+}
+
+inline size_t tile_lds_budget(int rb) { return rb <= 8 ? TB_LDS : TB_LDS_ONE; }
+
+// the per-column reductions at the end reuse the tiles: (B / 32) waves x 64 x PSR words
+inline size_t tile_red_lds(int rb) { return (size_t)(((size_t)1 << rb) / TB_RPW) * WAVE * PSR * sizeof(u64); }
+
+// local edges per range for which the edge buffer has room (0: the range size does not fit)
+inline int tile_le_max(int rb, int k, int tsize, bool weighted) {
+    if (rb < TB_MIN_RB || rb > TB_MAX_RB) return 0;
+    const size_t fixed = tile_bld_fixed_lds(rb, k, tsize, weighted), budget = tile_lds_budget(rb);
+    if (fixed + 256 * tile_edge_bytes(weighted) > budget) return 0;
+    const size_t le = (budget - fixed) / tile_edge_bytes(weighted);
+    return (int)std::min<size_t>(le & ~(size_t)3, 1 << 16);
+}
+
+inline size_t tile_bld_lds_launch(int rb, int k, int tsize, bool weighted) {
+    const size_t le = (size_t)tile_le_max(rb, k, tsize, weighted);
+    return std::max(tile_bld_fixed_lds(rb, k, tsize, weighted) + le * tile_edge_bytes(weighted), tile_red_lds(rb));
+}
+
+// Take the rows of act (bit u: row i0 + u, wave-uniform) of one scan group: every
+// running column's fluid f moves to the history (a workgroup-scope atomic add to the
+// row of H, which no other wave touches during the sweep) and is pushed along the row's
+// local edges; a row with cross-range edges also adds d f / s_i to its in-flight row S_i.
+// The first take of row i0 + u in this visit of the range (bit ubase + u of `taken`)
+// stores S_i, so that no earlier sweep's value survives, later takes add to it.
+template <typename T, bool WTD, int RU>
+__device__ __forceinline__ void tile_take_rows(const TileBldArgs &a, unsigned act, int i0, int ubase,
+                                               const T (&vv)[RU], unsigned &taken, bool col, bool colk, int lane,
+                                               int k, T *Fl, const unsigned *Deg, const unsigned *Off,
+                                               const double *Rw, const double *Inv, const unsigned short *Et,
+                                               const float *Ew, bool lds_edges, i64 base,
+                                               i64 lb, double &Rd, double &Ld, u64 &nodes, u64 &edges) {
+    T *S = reinterpret_cast<T *>(a.S);
+    double fu[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+        fu[u] = ((act >> u) & 1u) && col && vv[u] != (T)0 ? (double)atomicExch(&Fl[(i0 + u) * k + lane], (T)0) : 0.0;
+    for (int u = 0; u < RU; ++u) {
+        if (!((act >> u) & 1u)) continue;
+        const int i = i0 + u;
+        const i64 gi = base + i;
+        double f = fu[0];
+#pragma unroll
+        for (int v = 1; v < RU; ++v) f = u == v ? fu[v] : f;
+        nodes += lane == 0 ? 1 : 0;
+        if (f != 0.0) __hip_atomic_fetch_add(&a.H[gi * k + lane], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const unsigned dfl = Deg[i], deg = dfl & 0x7fffffffu;
+        if (deg == 0) {
+            Ld += f;
+            continue;
+        }
+        const double q = (a.d * f) * (WTD ? Inv[i] : 1.0 / (double)deg);
+        if (dfl & 0x80000000u) {
+            const T sv = (T)q;
+            const unsigned bit = 1u << (ubase + u);
+            if (taken & bit) {
+                if (sv != (T)0) __hip_atomic_fetch_add(&S[gi * k + lane], sv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                if (colk) S[gi * k + lane] = sv;
+                taken |= bit;
+            }
+            Rd += fabs((double)sv) * Rw[i];
+        }
+        const int st = (int)Off[i], ln = (int)Off[i + 1] - st;
+        const u64 fm = __ballot(f != 0.0);
+        edges += lane == 0 ? (u64)ln * (u64)__popcll(fm) : 0ull;
+        if (fm == 0) continue;
+        for (int eb = 0; eb < ln; eb += WAVE) {
+            const int c2 = min(WAVE, ln - eb);
+            const int pe = st + eb + min(lane, c2 - 1);
+            const int myt = lds_edges ? (int)Et[pe] : (int)a.loc_tgt[lb + pe];
+            const float myw = WTD ? (lds_edges ? Ew[pe] : a.loc_w[lb + pe]) : 1.0f;
+            for (int kk = 0; kk < c2; ++kk) {
+                const int t = __builtin_amdgcn_readlane(myt, kk);
+                const double val =
+                    WTD ? q * (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(myw), kk)) : q;
+                if (f != 0.0) atomicAdd(&Fl[t * k + lane], (T)val);
+            }
+        }
+    }
 }
 
 template <typename T, bool WTD>
-__global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
+__global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ u64 kred[2 * TB_WAVES];
+    __shared__ u64 kred[2 * TB_MAXW];
     const TileCtl *ctl = a.ctl;
     if (tile_stopped(ctl)) return;
-    const int B = 1 << a.rb, k = a.k;
+    const int B = 1 << a.rb, k = a.k, nthr = (int)blockDim.x;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
     const bool colk = lane < k;
     const bool col = colk && !ctl->done[lane];
     const double thr = col ? ctl->thr[lane] : 0.0;
     T *Fl = reinterpret_cast<T *>(smem);
-    double *Dl = reinterpret_cast<double *>(Fl + (size_t)B * k);
-    unsigned *Deg = reinterpret_cast<unsigned *>(Dl + (size_t)B * k);
+    unsigned *Deg = reinterpret_cast<unsigned *>(Fl + (size_t)B * k);
     unsigned *Off = Deg + B;
+    double *Rw = reinterpret_cast<double *>(smem + tile_rowdata_offset(a.rb, k, (int)sizeof(T)));
+    double *Inv = Rw + B;  // weighted graphs only
+    // edge buffer: weights (4-byte aligned) first, then the 16-bit targets
+    float *Ew = reinterpret_cast<float *>(WTD ? Inv + B : Inv);
+    unsigned short *Et = reinterpret_cast<unsigned short *>(WTD ? Ew + a.le_max : Ew);
     T *F = reinterpret_cast<T *>(a.F);
-    T *S = reinterpret_cast<T *>(a.S);
 
     // residual and leak: each lane (column) adds its values in double; the sums are
     // raised by 2^-30 relative (far above the rounding of up to 2^22 additions) and
-    // then enter the exact fixed-point sums, so the residual never falls short
+    // then enter the exact fixed-point sums, so the residual never falls short.  The
+    // fluid in flight enters as the sum of its parts' magnitudes.
     double Rd = 0.0, Ld = 0.0;
     u64 mx = 0, nodes = 0, edges = 0;
     int bad = 0;
@@ -335,37 +455,68 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
         const i64 base = (i64)r << a.rb;
         const int cnt = (int)min((i64)B, a.n - base);
         const i64 lb = a.loc_base[r];
+        const int ne = (int)(a.loc_ptr[base + cnt] - lb);
+        const bool lds_edges = ne <= a.le_max;
         // 1. stage: the range's fluid rows are one contiguous block of cnt * k values
+        // (256-byte aligned: ranges start at multiples of 64 rows), read in 16-byte units;
+        // each thread issues its loads of fluid, row data (B <= threads) and local edges
+        // before it stores any, so that their memory trips overlap
         {
-            constexpr int SU = 8;
-            const int tot = cnt * k;
-            const T *src = F + base * k;
-            for (int e0 = threadIdx.x; e0 < tot; e0 += TB_THREADS * SU) {
-                T v[SU];
+            constexpr int VE = 16 / (int)sizeof(T), SU = 8;
+            const int tot = cnt * k, nv = tot / VE;
+            const uint4 *srcv = reinterpret_cast<const uint4 *>(F + base * k);
+            uint4 *Flv = reinterpret_cast<uint4 *>(Fl);
+            const int i = threadIdx.x;
+            const bool row = i < cnt, offrow = i <= cnt;
+            const unsigned dv = row ? a.deg_flags[base + i] : 0u;
+            const i64 ov = offrow ? a.loc_ptr[base + i] : 0;
+            const double rv = row ? a.rw[base + i] : 0.0;
+            const double iv = WTD && row ? a.inv_s[base + i] : 0.0;
+            for (int e0 = threadIdx.x; e0 < nv; e0 += nthr * SU) {
+                uint4 v[SU];
 #pragma unroll
-                for (int u = 0; u < SU; ++u) v[u] = src[min(e0 + u * TB_THREADS, tot - 1)];
+                for (int u = 0; u < SU; ++u) v[u] = srcv[min(e0 + u * nthr, nv - 1)];
 #pragma unroll
-                for (int u = 0; u < SU; ++u) {
-                    const int e = e0 + u * TB_THREADS;
-                    if (e < tot) {
-                        Fl[e] = v[u];
-                        Dl[e] = 0.0;
+                for (int u = 0; u < SU; ++u)
+                    if (e0 + u * nthr < nv) Flv[e0 + u * nthr] = v[u];
+            }
+            for (int e = nv * VE + threadIdx.x; e < tot; e += nthr) Fl[e] = F[base * k + e];
+            if (row) {
+                Deg[i] = dv;
+                Rw[i] = rv;
+                if (WTD) Inv[i] = iv;
+            }
+            if (offrow) Off[i] = (unsigned)(ov - lb);
+            if (lds_edges) {
+                constexpr int EU = 8;
+                for (int e0 = threadIdx.x; e0 < ne; e0 += nthr * EU) {
+                    unsigned short tv[EU];
+                    float wv[EU];
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) {
+                        const int e = min(e0 + u * nthr, ne - 1);
+                        tv[u] = a.loc_tgt[lb + e];
+                        wv[u] = WTD ? a.loc_w[lb + e] : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) {
+                        const int e = e0 + u * nthr;
+                        if (e < ne) {
+                            Et[e] = tv[u];
+                            if (WTD) Ew[e] = wv[u];
+                        }
                     }
                 }
             }
-            for (int i = threadIdx.x; i <= cnt; i += TB_THREADS) {
-                if (i < cnt) Deg[i] = a.deg_flags[base + i];
-                Off[i] = (unsigned)(a.loc_ptr[base + i] - lb);
-            }
         }
         __syncthreads();
-        // 2. local rounds; wave w owns rows [my0, my1)
-        const int sub = (cnt + TB_WAVES - 1) / TB_WAVES;
-        const int my0 = min(cnt, w * sub), my1 = min(cnt, my0 + sub);
+        // 2. local rounds over the wave's rows [my0, my1), scanned RU at a time: their LDS
+        // values are read before any is taken
+        const int my0 = min(cnt, w * TB_RPW), my1 = min(cnt, my0 + TB_RPW);
+        constexpr int RU = 4;
+        unsigned taken = 0;
         for (int round = 0; round < a.rounds; ++round) {
             bool any = false;
-            // rows are scanned RU at a time: their LDS values are read before any is taken
-            constexpr int RU = 4;
             for (int i0 = my0; i0 < my1; i0 += RU) {
                 T vv[RU];
 #pragma unroll
@@ -377,87 +528,28 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
 #pragma unroll
                 for (int u = 0; u < RU; ++u)
                     if (__ballot(vv[u] != (T)0 && fabs((double)vv[u]) >= thr) != 0) act |= 1u << u;
-                if (act == 0) continue;
-                any = true;
-#pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    if (!((act >> u) & 1u)) continue;
-                    const int i = i0 + u;
-                    const T v = vv[u];
-                    const double f = col && v != (T)0 ? (double)atomicExch(&Fl[i * k + lane], (T)0) : 0.0;
-                    if (f != 0.0) Dl[i * k + lane] += f;
-                    nodes += lane == 0 ? 1 : 0;
-                    const unsigned deg = Deg[i] & 0x7fffffffu;
-                    if (deg == 0) {
-                        Ld += f;
-                        continue;
-                    }
-                    const double q = (a.d * f) * (WTD ? a.inv_s[base + i] : 1.0 / (double)deg);
-                    const int st = (int)Off[i], ln = (int)Off[i + 1] - st;
-                    const u64 fm = __ballot(f != 0.0);
-                    edges += lane == 0 ? (u64)ln * (u64)__popcll(fm) : 0ull;
-                    for (int eb = 0; eb < ln; eb += WAVE) {
-                        const int c2 = min(WAVE, ln - eb);
-                        const i64 pe = lb + st + eb + min(lane, c2 - 1);
-                        const int myt = (int)a.loc_tgt[pe];
-                        const float myw = WTD ? a.loc_w[pe] : 1.0f;
-                        for (int kk = 0; kk < c2; ++kk) {
-                            const int t = __builtin_amdgcn_readlane(myt, kk);
-                            const double val =
-                                WTD ? q * (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(myw), kk)) : q;
-                            if (f != 0.0) atomicAdd(&Fl[t * k + lane], (T)val);
-                        }
-                    }
+                if (act != 0) {
+                    any = true;
+                    tile_take_rows<T, WTD, RU>(a, act, i0, i0 - my0, vv, taken, col, colk, lane, k, Fl, Deg, Off, Rw, Inv, Et, Ew,
+                                               lds_edges, base, lb, Rd, Ld, nodes, edges);
                 }
             }
             if (!any) break;
         }
-        __syncthreads();
-        // 3. write back: a wave takes WU consecutive rows; their history rows (for the
-        // rows with an increment) are all loaded before any is stored
-        constexpr int WU = 4;
-        for (int i0 = w * WU; i0 < cnt; i0 += TB_WAVES * WU) {
-            T vv[WU];
-            double dd[WU];
-            double hv[WU], rwv[WU], invv[WU];
-            unsigned df[WU];
-#pragma unroll
-            for (int u = 0; u < WU; ++u) {
-                const int i = min(i0 + u, cnt - 1);
-                vv[u] = colk && i0 + u < cnt ? Fl[i * k + lane] : (T)0;
-                dd[u] = colk && i0 + u < cnt ? Dl[i * k + lane] : 0.0;
-                df[u] = i0 + u < cnt ? Deg[i] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < WU; ++u) {
-                const i64 gi = base + min(i0 + u, cnt - 1);
-                hv[u] = dd[u] != 0.0 ? a.H[gi * k + lane] : 0.0;
-                const bool remote = (df[u] & 0x80000000u) != 0;
-                rwv[u] = remote ? a.rw[gi] : 0.0;
-                invv[u] = remote ? (WTD ? a.inv_s[gi] : 1.0 / (double)(df[u] & 0x7fffffffu)) : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < WU; ++u) {
-                if (i0 + u >= cnt) break;
-                const i64 gi = base + i0 + u;
-                const T v = vv[u];
-                const double dh = dd[u];
-                if (colk) F[gi * k + lane] = v;
-                if (dh != 0.0) a.H[gi * k + lane] = hv[u] + dh;
-                Rd += fabs((double)v);
-                const u64 vb = (u64)__double_as_longlong(fabs((double)v));
-                mx = vb > mx ? vb : mx;
-                if (df[u] & 0x80000000u) {
-                    const T s = dh != 0.0 ? (T)((a.d * dh) * invv[u]) : (T)0;
-                    const bool fl = __ballot(s != (T)0) != 0;
-                    if (fl) {
-                        if (colk) S[gi * k + lane] = s;
-                        if (s != (T)0) Rd += fabs((double)s) * rwv[u];
-                    }
-                    if (lane == 0) a.fl[gi] = fl ? 1 : 0;
-                }
-            }
+        __syncthreads();  // every local push has landed
+        // 3. write back the wave's rows of F and their word of flags: bit i is set when row
+        // i was taken, so that its in-flight row (if it has cross-range edges) holds this
+        // sweep's fluid
+        for (int i = my0; i < my1; ++i) {
+            const i64 gi = base + i;
+            const T v = colk ? Fl[i * k + lane] : (T)0;
+            if (colk) F[gi * k + lane] = v;
+            Rd += fabs((double)v);
+            const u64 vb = (u64)__double_as_longlong(fabs((double)v));
+            mx = vb > mx ? vb : mx;
         }
+        // (the wave's 32 rows are one word: ranges start at multiples of 64)
+        if (lane == 0 && my0 < my1) a.fl[(base + my0) >> 5] = taken;
         __syncthreads();  // the next range reuses the LDS tiles
     }
     Limbs R, leak;
@@ -465,12 +557,13 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bld(TileBldArgs a) {
     limbs_zero(leak);
     if (!tile_limbs_add(R, Rd * (1.0 + 0x1p-30), a.K)) bad = 1;
     if (!tile_leak_add(leak, Ld, a.K)) bad = 1;
-    // the per-column reductions reuse the tile's LDS (TB_WAVES * 64 * PSR words)
+    // the per-column reductions reuse the tile's LDS (waves * 64 * PSR words)
+    const int nw = nthr / WAVE;
     u64 *red = reinterpret_cast<u64 *>(smem);
     u64 rv[PSR] = {R.l[0], R.l[1], R.l[2], R.l[3], mx};
-    block_columns_store<PSR, 1u << 4, TB_WAVES>(rv, red, a.partR + (i64)blockIdx.x * KMAX * PSR, k);
+    block_columns_store_n<PSR, 1u << 4>(rv, red, a.partR + (i64)blockIdx.x * KMAX * PSR, k, nw);
     u64 lv[4] = {leak.l[0], leak.l[1], leak.l[2], leak.l[3]};
-    block_columns_store<4, 0, TB_WAVES>(lv, red, a.partC + (i64)blockIdx.x * KMAX * 4, k);
+    block_columns_store_n<4, 0>(lv, red, a.partC + (i64)blockIdx.x * KMAX * 4, k, nw);
     u64 kv[2] = {nodes, edges};
     block_store_partials<2>(kv, kred, a.partK + (i64)blockIdx.x * 2);
     if (bad) atomicOr(&a.ctl->overflow, 1);
@@ -483,7 +576,7 @@ struct TileDlArgs {
     const int *rem_tgt;  // absolute target row of each entry
     const float *rem_w;
     const void *S;
-    const unsigned char *fl;
+    const unsigned *fl;
     void *F;
     const TileCtl *ctl;
     int k, force;
@@ -508,7 +601,7 @@ __global__ void __launch_bounds__(DL_THREADS) k_tile_deliver(TileDlArgs a) {
         const int src = a.rem_src[p];
         const int tgt = a.rem_tgt[p];
         const float ew = WTD ? a.rem_w[p] : 1.0f;
-        u64 m = __ballot(lane < un.len && a.fl[src] != 0);
+        u64 m = __ballot(lane < un.len && ((a.fl[src >> 5] >> (src & 31)) & 1u));
         delivered += lane == 0 ? (u64)__popcll(m) : 0ull;
         T run = (T)0;
         while (m) {
@@ -893,32 +986,36 @@ static int launch_tile_deliver(BatchState *b, const DevGraph &g, hipStream_t st)
 }
 
 static int launch_tile_bld(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
-    const TileBldArgs a = tile_bld_args(b, g, p);
-    const size_t lds = tile_bld_lds_launch(g.rb, b->k, b->fp32 ? 4 : 8);
+    TileBldArgs a = tile_bld_args(b, g, p);
+    const int T = b->fp32 ? 4 : 8;
+    a.le_max = tile_le_max(g.rb, b->k, T, g.weighted);
+    const size_t lds = tile_bld_lds_launch(g.rb, b->k, T, g.weighted);
+    const int threads = ((1 << g.rb) / TB_RPW) * WAVE;
     if (b->fp32) {
-        if (g.weighted) k_tile_bld<float, true><<<b->gridB, TB_THREADS, lds, st>>>(a);
-        else k_tile_bld<float, false><<<b->gridB, TB_THREADS, lds, st>>>(a);
+        if (g.weighted) k_tile_bld<float, true><<<b->gridB, threads, lds, st>>>(a);
+        else k_tile_bld<float, false><<<b->gridB, threads, lds, st>>>(a);
     } else {
-        if (g.weighted) k_tile_bld<double, true><<<b->gridB, TB_THREADS, lds, st>>>(a);
-        else k_tile_bld<double, false><<<b->gridB, TB_THREADS, lds, st>>>(a);
+        if (g.weighted) k_tile_bld<double, true><<<b->gridB, threads, lds, st>>>(a);
+        else k_tile_bld<double, false><<<b->gridB, threads, lds, st>>>(a);
     }
     DI_LAUNCH_CHECK();
     return DI_OK;
 }
 
-int tile_range_log2(int k, int fp32) {
-    for (int rb = 11; rb >= 6; --rb)
-        if (tile_bld_lds(rb, k, fp32 ? 4 : 8) <= TB_LDS) return rb;
+// the largest range size whose tiles let two workgroups share a compute unit
+int tile_range_log2(int k, int fp32, int weighted) {
+    for (int rb = 8; rb >= TB_MIN_RB; --rb)
+        if (tile_le_max(rb, k, fp32 ? 4 : 8, weighted != 0) >= 1024) return rb;
     return 0;
 }
 
 static int set_tile_attributes() {
     static bool done = false;
     if (done) return DI_OK;
-    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS));
-    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS));
-    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS));
-    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS));
+    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS_ONE));
+    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS_ONE));
+    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS_ONE));
+    DI_HIP(hipFuncSetAttribute((const void *)k_tile_bld<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TB_LDS_ONE));
     done = true;
     return DI_OK;
 }
@@ -1147,18 +1244,18 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
     b->gridP = (int)std::min<i64>(TILE_GRID, (n + TILE_WAVES - 1) / TILE_WAVES);
     b->gridR = (int)std::min<i64>(REDUCE_TILE_GRID, (n + TILE_WAVES - 1) / TILE_WAVES);
     // fast sweeps are block-local when a range's fluid and dH tiles fit in LDS
-    b->bld = !det && g.rb >= 6 && tile_bld_lds_launch(g.rb, k, (int)T) <= TB_LDS;
+    b->bld = !det && tile_le_max(g.rb, k, (int)T, g.weighted) > 0;
     b->rounds = rounds > 0 ? rounds : 4;
     (void)range_order;
     if (b->bld) {
-        // as many resident workgroups as the compute units' LDS holds (160 KB each);
-        // ranges are dealt out longest first, each to the least loaded workgroup
+        // one resident workgroup per compute unit and LDS share (two up to 2^8-row
+        // ranges); ranges are dealt out longest first, each to the least loaded workgroup
         int cus = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 256;
-        const int per_cu = std::max(1, (int)((160 * 1024) / (tile_bld_lds_launch(g.rb, k, (int)T) + 1024)));
-        b->gridB = (int)std::min<i64>(std::min<i64>((i64)cus * std::min(per_cu, 2), TB_GRID), g.nranges);
+        const int per_cu = g.rb <= 8 ? 2 : 1;
+        b->gridB = (int)std::min<i64>(std::min<i64>((i64)cus * per_cu, TB_GRID), g.nranges);
     }
     const size_t slots = (size_t)std::max(std::max(b->gridR, b->gridP), b->gridB + DL_GRID);
     auto fail = [&](int code) {
@@ -1177,7 +1274,7 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
         (det && !alloc((void **)&b->snap, n * k * 8)))
         return fail(DI_ENOMEM);
     if (b->bld) {
-        if (!alloc(&b->S, n * k * T) || !alloc((void **)&b->fl, n) ||
+        if (!alloc(&b->S, n * k * T) || !alloc((void **)&b->fl, (size_t)((n + 31) / 32) * 4) ||
             !alloc((void **)&b->blk_ptr, (size_t)(b->gridB + 1) * 4) ||
             !alloc((void **)&b->blk_ranges, (size_t)g.nranges * 4))
             return fail(DI_ENOMEM);
@@ -1208,7 +1305,7 @@ int reset_batch(BatchState *b, const DevGraph &g, const SweepParams &p, hipStrea
     DI_TRY(launch_init_fluid(b->F0, b->F, b->fp32, b->n * b->k, st));
     DI_TRY(launch_fill_zero(b->H, b->n * b->k * 8, st));
     DI_TRY(launch_fill_zero(b->ctl, sizeof(TileCtl), st));
-    if (b->bld) DI_TRY(launch_fill_zero(b->fl, b->n, st));
+    if (b->bld) DI_TRY(launch_fill_zero(b->fl, ((b->n + 31) / 32) * 4, st));
     DI_TRY(launch_tile_reduce(b, tile_args(b, g, p), 1, st));
     DI_TRY(launch_tile_finalize(b, p, FIN_INIT, b->gridR, 0, 0, st));
     DI_HIP(hipStreamSynchronize(st));

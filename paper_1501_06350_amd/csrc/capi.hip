@@ -825,8 +825,9 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     const int rbmax = opt.fluid_fp32 ? 14 : 13;
     int rb = opt.range_log2;
     if (rb == 0 && opt.k > 1 && !opt.deterministic) {
-        // several columns: ranges whose k-column fluid and dH tiles fit in LDS
-        rb = tile_range_log2(opt.k, opt.fluid_fp32);
+        // several columns: ranges whose k-column fluid tile and local edge lists fit in
+        // half of a compute unit's LDS
+        rb = tile_range_log2(opt.k, opt.fluid_fp32, w != nullptr);
         if (rb == 0) rb = 8;
     } else if (rb == 0) {
         const int cap = w ? rbmax : 11;
