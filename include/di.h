@@ -70,10 +70,10 @@ typedef struct {
  *   max_sweeps     : sweep (or iteration) budget per di_diffuse / di_power call [100000]
  *   deterministic  : 1 = synchronous sweeps with snapshot semantics and ordered
  *                    accumulation (bit-reproducible, slower) [0]
- *   range_log2     : block-local range size 2^range_log2 nodes, 8..14 (f32 fluid) or
- *                    8..13 (0 = auto).  With k > 1: 6..9 runs the tile's block-local
- *                    sweep (auto: the largest range whose fluid tile lets two
- *                    workgroups share a compute unit), larger sizes its plain push sweep
+ *   range_log2     : block-local range size 2^range_log2 nodes, 8..13 (0 = auto).
+ *                    With k > 1: 6..8 runs the tile's block-local sweep (auto: the
+ *                    largest range whose fluid tile lets two workgroups share a compute
+ *                    unit), larger sizes its plain push sweep
  *   inner_rounds   : block-local diffusion rounds per sweep, 1..64 (0 = auto)
  *   k              : number of right-hand sides (columns of Z), 1..64 [1].  k > 1
  *                    diffuses an n x k fluid tile (personalized PageRank, Section 2.1):

@@ -267,10 +267,11 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
 // ---------------------------------------------------------------------------
 // Block-local fast sweep of the tile, in two kernels per sweep.
 //
-// k_tile_bld: node ids are grouped into ranges of B = 2^rb rows; a workgroup of B / 32
-// waves takes its ranges one after another, wave w owning rows [32 w, 32 w + 32) of a
-// range.  The range's fluid tile F[B][k] (fluid type) and its local edge lists sit in
-// LDS; lane c of a wave holds column c.  For a range it
+// k_tile_bld: node ids are grouped into ranges of B = 2^rb rows; a workgroup of B / 16
+// waves takes its ranges one after another, wave w owning rows [16 w, 16 w + 16) of a
+// range.  The range's fluid tile F[B][k] (double in LDS, whatever the fluid type in
+// memory) and its local edge lists sit in LDS; lane c of a wave holds column c.  For a
+// range it
 //   1. stages the fluid rows (they already hold what other ranges sent last sweep) and
 //      the targets (and weights) of the range's local edges;
 //   2. runs up to `rounds` local rounds: each wave scans its rows, takes a row when some
@@ -288,17 +289,19 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
 // the per-XCD L2 caches.  The residual of every column, |F|_1 plus the fluid in
 // flight, is summed at write-back; delivery moves fluid without changing it.
 // ---------------------------------------------------------------------------
-// Ranges of up to 2^8 rows run two workgroups per compute unit (one stages or writes
-// back a range while the other runs local rounds), each within TB_LDS of LDS; 2^9-row
-// ranges run one workgroup of 16 waves per compute unit with up to TB_LDS_ONE.
-constexpr int TB_RPW = 32;  // rows per wave (at most 32: one bit each in a wave-uniform mask)
-constexpr int TB_MAXW = 16; // waves per workgroup at 2^9-row ranges
-static_assert(TB_RPW == 32 && (1 << 6) % TB_RPW == 0, "a wave's rows are one 32-bit word of flags");
+// The LDS tile holds the fluid in double whatever the fluid type in memory: on this chip
+// a 64-lane LDS atomic add costs about 8 cycles in double and about 190 in float.  A
+// range whose tiles fit TB_LDS runs two workgroups per compute unit (one stages or writes
+// back a range while the other runs local rounds); larger ones one workgroup, within
+// TB_LDS_ONE.  A wave owns 16 rows, so a workgroup has 2^rb / 16 waves.
+constexpr int TB_RPW = 16;  // rows per wave: one bit each in a wave-uniform mask, one 16-bit word of flags
+constexpr int TB_MAXW = 16; // waves per workgroup at 2^8-row ranges
 constexpr int TB_MAX_THREADS = TB_MAXW * WAVE;
 constexpr int TB_GRID = 1024;
 constexpr size_t TB_LDS = 78 * 1024;
 constexpr size_t TB_LDS_ONE = 156 * 1024;
-constexpr int TB_MIN_RB = 6, TB_MAX_RB = 9;
+constexpr int TB_MIN_RB = 6, TB_MAX_RB = 8;
+static_assert(TB_RPW == 16 && ((1 << TB_MAX_RB) / TB_RPW) <= TB_MAXW, "waves per workgroup");
 constexpr int DL_THREADS = 256;
 constexpr int DL_WAVES = DL_THREADS / WAVE;
 constexpr int DL_GRID = 4096;
@@ -327,36 +330,66 @@ struct TileBldArgs {
 
 inline size_t tile_edge_bytes(bool weighted) { return weighted ? 6 : 2; }
 
-// LDS of a range (the edge buffer comes on top): the fluid tile, degrees and local row
-// offsets (u32), then per row the out-weight of its cross-range edges and, for weighted
-// graphs, 1/s_i (doubles, 8-byte aligned)
-__host__ __device__ inline size_t tile_rowdata_offset(int rb, int k, int tsize) {
+// LDS of a range (the edge buffer comes on top): the fluid tile (double), degrees and
+// local row offsets (u32), then per row the out-weight of its cross-range edges and, for
+// weighted graphs, 1/s_i (doubles, 8-byte aligned)
+__host__ __device__ inline size_t tile_rowdata_offset(int rb, int k) {
     const size_t B = (size_t)1 << rb;
-    return (B * k * tsize + (2 * B + 1) * 4 + 7) & ~(size_t)7;
+    return (B * k * 8 + (2 * B + 1) * 4 + 7) & ~(size_t)7;
 }
 
-__host__ __device__ inline size_t tile_bld_fixed_lds(int rb, int k, int tsize, bool weighted) {
+__host__ __device__ inline size_t tile_bld_fixed_lds(int rb, int k, bool weighted) {
     const size_t B = (size_t)1 << rb;
-    return tile_rowdata_offset(rb, k, tsize) + B * 8 * (weighted ? 2 : 1) + 16;
+    return tile_rowdata_offset(rb, k) + B * 8 * (weighted ? 2 : 1) + 16;
 }
 
-inline size_t tile_lds_budget(int rb) { return rb <= 8 ? TB_LDS : TB_LDS_ONE; }
+// two workgroups per compute unit when the tiles and 1024 local edges fit TB_LDS
+inline bool tile_two_per_cu(int rb, int k, bool weighted) {
+    return tile_bld_fixed_lds(rb, k, weighted) + 1024 * tile_edge_bytes(weighted) <= TB_LDS;
+}
 
-// the per-column reductions at the end reuse the tiles: (B / 32) waves x 64 x PSR words
+inline size_t tile_lds_budget(int rb, int k, bool weighted) {
+    return tile_two_per_cu(rb, k, weighted) ? TB_LDS : TB_LDS_ONE;
+}
+
+// the per-column reductions at the end reuse the tiles: (B / 16) waves x 64 x PSR words
 inline size_t tile_red_lds(int rb) { return (size_t)(((size_t)1 << rb) / TB_RPW) * WAVE * PSR * sizeof(u64); }
 
 // local edges per range for which the edge buffer has room (0: the range size does not fit)
-inline int tile_le_max(int rb, int k, int tsize, bool weighted) {
+inline int tile_le_max(int rb, int k, bool weighted) {
     if (rb < TB_MIN_RB || rb > TB_MAX_RB) return 0;
-    const size_t fixed = tile_bld_fixed_lds(rb, k, tsize, weighted), budget = tile_lds_budget(rb);
+    const size_t fixed = tile_bld_fixed_lds(rb, k, weighted), budget = tile_lds_budget(rb, k, weighted);
     if (fixed + 256 * tile_edge_bytes(weighted) > budget) return 0;
     const size_t le = (budget - fixed) / tile_edge_bytes(weighted);
     return (int)std::min<size_t>(le & ~(size_t)3, 1 << 16);
 }
 
-inline size_t tile_bld_lds_launch(int rb, int k, int tsize, bool weighted) {
-    const size_t le = (size_t)tile_le_max(rb, k, tsize, weighted);
-    return std::max(tile_bld_fixed_lds(rb, k, tsize, weighted) + le * tile_edge_bytes(weighted), tile_red_lds(rb));
+inline size_t tile_bld_lds_launch(int rb, int k, bool weighted) {
+    const size_t le = (size_t)tile_le_max(rb, k, weighted);
+    return std::max(tile_bld_fixed_lds(rb, k, weighted) + le * tile_edge_bytes(weighted), tile_red_lds(rb));
+}
+
+// a 16-byte unit of fluid (4 floats or 2 doubles) into the double LDS tile
+template <typename T>
+__device__ __forceinline__ void tile_lds_unit(double *dst, const uint4 &v) {
+    if constexpr (sizeof(T) == 4) {
+        dst[0] = (double)__uint_as_float(v.x);
+        dst[1] = (double)__uint_as_float(v.y);
+        dst[2] = (double)__uint_as_float(v.z);
+        dst[3] = (double)__uint_as_float(v.w);
+    } else {
+        dst[0] = __hiloint2double((int)v.y, (int)v.x);
+        dst[1] = __hiloint2double((int)v.w, (int)v.z);
+    }
+}
+
+// Workgroup barrier that orders LDS accesses only: it does not wait for the waves'
+// outstanding global stores and atomics (the tile sweep's rows of H, S, F and flags are
+// not read back by any wave of the launch).
+__device__ __forceinline__ void block_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Take the rows of act (bit u: row i0 + u, wave-uniform) of one scan group: every
@@ -367,8 +400,8 @@ inline size_t tile_bld_lds_launch(int rb, int k, int tsize, bool weighted) {
 // stores S_i, so that no earlier sweep's value survives, later takes add to it.
 template <typename T, bool WTD, int RU>
 __device__ __forceinline__ void tile_take_rows(const TileBldArgs &a, unsigned act, int i0, int ubase,
-                                               const T (&vv)[RU], unsigned &taken, bool col, bool colk, int lane,
-                                               int k, T *Fl, const unsigned *Deg, const unsigned *Off,
+                                               const double (&vv)[RU], unsigned &taken, bool col, bool colk, int lane,
+                                               int k, double *Fl, const unsigned *Deg, const unsigned *Off,
                                                const double *Rw, const double *Inv, const unsigned short *Et,
                                                const float *Ew, bool lds_edges, i64 base,
                                                i64 lb, double &Rd, double &Ld, u64 &nodes, u64 &edges) {
@@ -376,7 +409,7 @@ __device__ __forceinline__ void tile_take_rows(const TileBldArgs &a, unsigned ac
     double fu[RU];
 #pragma unroll
     for (int u = 0; u < RU; ++u)
-        fu[u] = ((act >> u) & 1u) && col && vv[u] != (T)0 ? (double)atomicExch(&Fl[(i0 + u) * k + lane], (T)0) : 0.0;
+        fu[u] = ((act >> u) & 1u) && col && vv[u] != 0.0 ? atomicExch(&Fl[(i0 + u) * k + lane], 0.0) : 0.0;
     for (int u = 0; u < RU; ++u) {
         if (!((act >> u) & 1u)) continue;
         const int i = i0 + u;
@@ -416,7 +449,7 @@ __device__ __forceinline__ void tile_take_rows(const TileBldArgs &a, unsigned ac
                 const int t = __builtin_amdgcn_readlane(myt, kk);
                 const double val =
                     WTD ? q * (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(myw), kk)) : q;
-                if (f != 0.0) atomicAdd(&Fl[t * k + lane], (T)val);
+                if (f != 0.0) atomicAdd(&Fl[t * k + lane], val);
             }
         }
     }
@@ -433,10 +466,10 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
     const bool colk = lane < k;
     const bool col = colk && !ctl->done[lane];
     const double thr = col ? ctl->thr[lane] : 0.0;
-    T *Fl = reinterpret_cast<T *>(smem);
+    double *Fl = reinterpret_cast<double *>(smem);
     unsigned *Deg = reinterpret_cast<unsigned *>(Fl + (size_t)B * k);
     unsigned *Off = Deg + B;
-    double *Rw = reinterpret_cast<double *>(smem + tile_rowdata_offset(a.rb, k, (int)sizeof(T)));
+    double *Rw = reinterpret_cast<double *>(smem + tile_rowdata_offset(a.rb, k));
     double *Inv = Rw + B;  // weighted graphs only
     // edge buffer: weights (4-byte aligned) first, then the 16-bit targets
     float *Ew = reinterpret_cast<float *>(WTD ? Inv + B : Inv);
@@ -465,7 +498,6 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
             constexpr int VE = 16 / (int)sizeof(T), SU = 8;
             const int tot = cnt * k, nv = tot / VE;
             const uint4 *srcv = reinterpret_cast<const uint4 *>(F + base * k);
-            uint4 *Flv = reinterpret_cast<uint4 *>(Fl);
             const int i = threadIdx.x;
             const bool row = i < cnt, offrow = i <= cnt;
             const unsigned dv = row ? a.deg_flags[base + i] : 0u;
@@ -478,9 +510,9 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
                 for (int u = 0; u < SU; ++u) v[u] = srcv[min(e0 + u * nthr, nv - 1)];
 #pragma unroll
                 for (int u = 0; u < SU; ++u)
-                    if (e0 + u * nthr < nv) Flv[e0 + u * nthr] = v[u];
+                    if (e0 + u * nthr < nv) tile_lds_unit<T>(Fl + (size_t)(e0 + u * nthr) * VE, v[u]);
             }
-            for (int e = nv * VE + threadIdx.x; e < tot; e += nthr) Fl[e] = F[base * k + e];
+            for (int e = nv * VE + threadIdx.x; e < tot; e += nthr) Fl[e] = (double)F[base * k + e];
             if (row) {
                 Deg[i] = dv;
                 Rw[i] = rv;
@@ -509,7 +541,7 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
                 }
             }
         }
-        __syncthreads();
+        block_sync_lds();
         // 2. local rounds over the wave's rows [my0, my1), scanned RU at a time: their LDS
         // values are read before any is taken
         const int my0 = min(cnt, w * TB_RPW), my1 = min(cnt, my0 + TB_RPW);
@@ -518,16 +550,16 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
         for (int round = 0; round < a.rounds; ++round) {
             bool any = false;
             for (int i0 = my0; i0 < my1; i0 += RU) {
-                T vv[RU];
+                double vv[RU];
 #pragma unroll
                 for (int u = 0; u < RU; ++u)
                     vv[u] = col && i0 + u < my1
                                 ? __hip_atomic_load(&Fl[(i0 + u) * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                                : (T)0;
+                                : 0.0;
                 unsigned act = 0;
 #pragma unroll
                 for (int u = 0; u < RU; ++u)
-                    if (__ballot(vv[u] != (T)0 && fabs((double)vv[u]) >= thr) != 0) act |= 1u << u;
+                    if (__ballot(vv[u] != 0.0 && fabs(vv[u]) >= thr) != 0) act |= 1u << u;
                 if (act != 0) {
                     any = true;
                     tile_take_rows<T, WTD, RU>(a, act, i0, i0 - my0, vv, taken, col, colk, lane, k, Fl, Deg, Off, Rw, Inv, Et, Ew,
@@ -536,21 +568,22 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
             }
             if (!any) break;
         }
-        __syncthreads();  // every local push has landed
+        block_sync_lds();  // every local push has landed
         // 3. write back the wave's rows of F and their word of flags: bit i is set when row
         // i was taken, so that its in-flight row (if it has cross-range edges) holds this
         // sweep's fluid
         for (int i = my0; i < my1; ++i) {
             const i64 gi = base + i;
-            const T v = colk ? Fl[i * k + lane] : (T)0;
+            const T v = colk ? (T)Fl[i * k + lane] : (T)0;
             if (colk) F[gi * k + lane] = v;
             Rd += fabs((double)v);
             const u64 vb = (u64)__double_as_longlong(fabs((double)v));
             mx = vb > mx ? vb : mx;
         }
-        // (the wave's 32 rows are one word: ranges start at multiples of 64)
-        if (lane == 0 && my0 < my1) a.fl[(base + my0) >> 5] = taken;
-        __syncthreads();  // the next range reuses the LDS tiles
+        // (the wave's 16 rows are one 16-bit half of a flag word: ranges start at
+        // multiples of 64)
+        if (lane == 0 && my0 < my1) reinterpret_cast<unsigned short *>(a.fl)[(base + my0) >> 4] = (unsigned short)taken;
+        block_sync_lds();  // the next range reuses the LDS tiles
     }
     Limbs R, leak;
     limbs_zero(R);
@@ -988,8 +1021,8 @@ static int launch_tile_deliver(BatchState *b, const DevGraph &g, hipStream_t st)
 static int launch_tile_bld(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
     TileBldArgs a = tile_bld_args(b, g, p);
     const int T = b->fp32 ? 4 : 8;
-    a.le_max = tile_le_max(g.rb, b->k, T, g.weighted);
-    const size_t lds = tile_bld_lds_launch(g.rb, b->k, T, g.weighted);
+    a.le_max = tile_le_max(g.rb, b->k, g.weighted);
+    const size_t lds = tile_bld_lds_launch(g.rb, b->k, g.weighted);
     const int threads = ((1 << g.rb) / TB_RPW) * WAVE;
     if (b->fp32) {
         if (g.weighted) k_tile_bld<float, true><<<b->gridB, threads, lds, st>>>(a);
@@ -1002,10 +1035,14 @@ static int launch_tile_bld(BatchState *b, const DevGraph &g, const SweepParams &
     return DI_OK;
 }
 
-// the largest range size whose tiles let two workgroups share a compute unit
+// the largest range size whose tiles let two workgroups share a compute unit, else the
+// largest that fits one (the LDS tile is double for either fluid type)
 int tile_range_log2(int k, int fp32, int weighted) {
-    for (int rb = 8; rb >= TB_MIN_RB; --rb)
-        if (tile_le_max(rb, k, fp32 ? 4 : 8, weighted != 0) >= 1024) return rb;
+    (void)fp32;
+    for (int rb = TB_MAX_RB; rb >= TB_MIN_RB; --rb)
+        if (tile_two_per_cu(rb, k, weighted != 0)) return rb;
+    for (int rb = TB_MAX_RB; rb >= TB_MIN_RB; --rb)
+        if (tile_le_max(rb, k, weighted != 0) >= 1024) return rb;
     return 0;
 }
 
@@ -1244,17 +1281,17 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
     b->gridP = (int)std::min<i64>(TILE_GRID, (n + TILE_WAVES - 1) / TILE_WAVES);
     b->gridR = (int)std::min<i64>(REDUCE_TILE_GRID, (n + TILE_WAVES - 1) / TILE_WAVES);
     // fast sweeps are block-local when a range's fluid and dH tiles fit in LDS
-    b->bld = !det && tile_le_max(g.rb, k, (int)T, g.weighted) > 0;
+    b->bld = !det && tile_le_max(g.rb, k, g.weighted) > 0;
     b->rounds = rounds > 0 ? rounds : 4;
     (void)range_order;
     if (b->bld) {
-        // one resident workgroup per compute unit and LDS share (two up to 2^8-row
-        // ranges); ranges are dealt out longest first, each to the least loaded workgroup
+        // one resident workgroup per compute unit and LDS share (two when the tiles fit
+        // TB_LDS); ranges are dealt out longest first, each to the least loaded workgroup
         int cus = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 256;
-        const int per_cu = g.rb <= 8 ? 2 : 1;
+        const int per_cu = tile_two_per_cu(g.rb, k, g.weighted) ? 2 : 1;
         b->gridB = (int)std::min<i64>(std::min<i64>((i64)cus * per_cu, TB_GRID), g.nranges);
     }
     const size_t slots = (size_t)std::max(std::max(b->gridR, b->gridP), b->gridB + DL_GRID);

@@ -754,7 +754,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     if (opt.max_sweeps < 0) DI_FAIL(DI_EINVAL, "max_sweeps must be >= 0");
     if (opt.max_sweeps == 0) opt.max_sweeps = 100000;
     {
-        const int lo = opt.k > 1 ? 6 : 8, hi = opt.fluid_fp32 ? 14 : 13;
+        const int lo = opt.k > 1 ? 6 : 8, hi = 13;
         if (opt.range_log2 != 0 && (opt.range_log2 < lo || opt.range_log2 > hi))
             DI_FAIL(DI_EINVAL, "range_log2 must be 0 or in %d..%d", lo, hi);
     }
@@ -822,7 +822,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     // block-local range size: unweighted graphs use the LDS-resident kernel with 2^11-node
     // ranges; weighted graphs the largest range whose fluid fits in LDS; small graphs keep
     // at least ~256 nodes per range so that several workgroups run
-    const int rbmax = opt.fluid_fp32 ? 14 : 13;
+    const int rbmax = 13;  // two 2^13-node double tiles of the weighted sweep fill its LDS
     int rb = opt.range_log2;
     if (rb == 0 && opt.k > 1 && !opt.deterministic) {
         // several columns: ranges whose k-column fluid tile and local edge lists fit in

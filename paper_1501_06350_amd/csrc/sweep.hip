@@ -26,10 +26,13 @@ constexpr int BLD_WAVES = BLD_THREADS / WAVE;
 
 int bld_threads() { return BLD_THREADS; }
 
+// The LDS tiles of the block-local sweeps hold the fluid in double for every fluid type:
+// on this chip a 64-lane LDS atomic add costs about 8 cycles in double and about 190 in
+// float.  The fluid type decides only what is stored in memory.
 size_t bld_lds_bytes(int rb, int fp32) {
+    (void)fp32;
     const size_t B = (size_t)1 << rb;
-    const size_t T = fp32 ? 4 : 8;
-    return 2 * B * T + (size_t)BLD_WAVES * WAVE * (8 + 4 + 8);
+    return 2 * B * 8 + (size_t)BLD_WAVES * WAVE * (8 + 4 + 8);
 }
 
 template <typename T>
@@ -134,8 +137,8 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
     if (!a.force && (ctl->done || ctl->sweep >= ctl->budget)) return;
     const int B = 1 << a.rb;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
-    T *Fl = reinterpret_cast<T *>(smem);
-    T *Sl = Fl + B;
+    double *Fl = reinterpret_cast<double *>(smem);
+    double *Sl = Fl + B;
     i64 *sc_start = reinterpret_cast<i64 *>(Sl + B) + w * WAVE;
     int *sc_off = reinterpret_cast<int *>(reinterpret_cast<i64 *>(Sl + B) + BLD_WAVES * WAVE) + w * WAVE;
     double *sc_q =
@@ -162,8 +165,8 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
 
     // 1. fluid of the range, plus fluid sent here by other ranges last sweep
     for (int i = threadIdx.x; i < cnt; i += BLD_THREADS) {
-        Fl[i] = F[base + i];
-        Sl[i] = (T)0;
+        Fl[i] = (double)F[base + i];
+        Sl[i] = 0.0;
     }
     __syncthreads();
     u64 delivered = 0;
@@ -194,9 +197,9 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
 #pragma unroll
             for (int u = 0; u < REM_U; ++u) {
                 if (pb + (i64)u * BLD_THREADS < p1 && v[u] != (T)0) {
-                    T add = v[u];
-                    if (WTD) add = (T)((double)add * (double)wv[u]);
-                    if (ADJ) add = (T)((double)add * a.tinv[base + tg[u]]);
+                    double add = (double)v[u];
+                    if (WTD) add *= (double)wv[u];
+                    if (ADJ) add *= a.tinv[base + tg[u]];
                     atomicAdd(&Fl[tg[u]], add);
                     ++delivered;
                 }
@@ -223,8 +226,8 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
             const int i = c + lane;
             double f = 0.0;
             if (i < my1) {
-                T v = lds_load(&Fl[i]);
-                if (v != (T)0 && fabs((double)v) >= thr) f = (double)atomicExch(&Fl[i], (T)0);
+                const double v = lds_load(&Fl[i]);
+                if (v != 0.0 && fabs(v) >= thr) f = atomicExch(&Fl[i], 0.0);
             }
             if (__ballot(f != 0.0) == 0) continue;
             any = true;
@@ -239,7 +242,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
                     if (!limbs_add_signed_checked(leak, f, a.K)) bad = 1;
                 } else {
                     q = ADJ ? a.d * f : (a.d * f) * inv;
-                    if (a.rw[gi] > 0.0) Sl[i] = (T)((double)Sl[i] + q);
+                    if (a.rw[gi] > 0.0) Sl[i] += q;
                     st = a.loc_ptr[gi];
                     dg = (int)(a.loc_ptr[gi + 1] - st);
                 }
@@ -277,7 +280,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
                 }
 #pragma unroll
                 for (int u = 0; u < EDGE_U; ++u)
-                    if (sb + u * WAVE < total) atomicAdd(&Fl[tgt[u]], (T)val[u]);
+                    if (sb + u * WAVE < total) atomicAdd(&Fl[tgt[u]], val[u]);
             }
             wave_sync_lds();
         }
@@ -289,8 +292,8 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
     Limbs R;
     limbs_zero(R);
     for (int i = threadIdx.x; i < cnt; i += BLD_THREADS) {
-        const T v = Fl[i];
-        const T s = Sl[i];
+        const T v = (T)Fl[i];
+        const T s = (T)Sl[i];
         F[base + i] = v;
         // the wave's 64 lanes hold 64 consecutive nodes starting at a multiple of 64
         const u64 bits = __ballot(s != (T)0);
@@ -375,11 +378,12 @@ struct Bld2Args {
     const GraphCtl *gctl;
 };
 
-// LDS layout of k_bld2_sweep (bytes): F[B] (fluid type), dH[B] (double), deg[B], off[B+1]
+// LDS layout of k_bld2_sweep (bytes): F[B] (double), dH[B] (double), deg[B], off[B+1]
 // (u32), padding to 8, then per wave 64 x (q double, start u32), per wave a bitmap of
 // BLD2_SLOTS bits, then the targets.
 __host__ __device__ inline size_t bld2_scratch_offset(int B, int tsize) {
-    return ((size_t)B * tsize + (size_t)8 * B + (size_t)4 * (2 * B + 1) + 7) & ~(size_t)7;
+    (void)tsize;  // the LDS fluid is double for every fluid type
+    return ((size_t)B * 8 + (size_t)8 * B + (size_t)4 * (2 * B + 1) + 7) & ~(size_t)7;
 }
 
 // edge slots one wave lists before it pushes them (a multiple of 4 x 64)
@@ -457,8 +461,8 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     const int B = 1 << a.rb;
     const int nthr = blockDim.x, nw = nthr >> 6;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
-    T *Fl = reinterpret_cast<T *>(smem);
-    double *Dl = reinterpret_cast<double *>(Fl + B);  // history increments, double for every fluid type
+    double *Fl = reinterpret_cast<double *>(smem);  // double for every fluid type
+    double *Dl = Fl + B;                            // history increments
     unsigned *Deg = reinterpret_cast<unsigned *>(Dl + B);
     unsigned *Off = Deg + B;  // B + 1 entries
     double *sc_q_all = reinterpret_cast<double *>(smem + bld2_scratch_offset(B, (int)sizeof(T)));
@@ -508,7 +512,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
         for (int u = 0; u < SU; ++u) {
             const int i = i0 + u * nthr;
             if (i < cnt) {
-                Fl[i] = fv[u];
+                Fl[i] = (double)fv[u];
                 Dl[i] = 0.0;
                 Deg[i] = dv[u];
             }
@@ -572,7 +576,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
 #pragma unroll
             for (int u = 0; u < REM_U; ++u) {
                 if (pb + (i64)u * nthr < p1 && v[u] != (T)0) {
-                    atomicAdd(&Fl[tg[u]], v[u]);
+                    atomicAdd(&Fl[tg[u]], (double)v[u]);
                     ++delivered;
                 }
             }
@@ -606,12 +610,12 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             const int ii = own ? i : c;  // lanes past the range load the chunk's first node
             // the node's degree, offsets and 1/degree load and compute while its fluid
             // value is read
-            const T v = lds_load(&Fl[ii]);
+            const double v = lds_load(&Fl[ii]);
             const unsigned deg = Deg[ii] & 0x7fffffffu;
             const unsigned o0 = Off[ii], o1 = Off[ii + 1];
             const double rdeg = recip_count(deg ? deg : 1u);
             double f = 0.0;
-            if (own && v != (T)0 && fabs((double)v) >= thr) f = (double)atomicExch(&Fl[i], (T)0);
+            if (own && v != 0.0 && fabs(v) >= thr) f = atomicExch(&Fl[i], 0.0);
             if (__ballot(f != 0.0) == 0) continue;
             any = true;
             int dg = 0;
@@ -639,7 +643,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             const int rk = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(pm >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((unsigned)pm, 0u));
             if (ln + nact > WAVE || ltot + total > BLD2_SLOTS) {
-                bld2_push_list<T>(Fl, Tg, tdelta, ncap, nloc, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start),
+                bld2_push_list<double>(Fl, Tg, tdelta, ncap, nloc, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start),
                                   sc_q, sc_bits, ltot, lane);
                 ln = 0;
                 ltot = 0;
@@ -664,7 +668,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
                 const int dg_n = __builtin_amdgcn_readlane(dg, src);
                 const unsigned q_lo = (unsigned)__builtin_amdgcn_readlane((int)qb, src);
                 const int q_hi = __builtin_amdgcn_readlane((int)(qb >> 32), src);
-                const T val = (T)__longlong_as_double(((long long)q_hi << 32) | (long long)q_lo);
+                const double val = __longlong_as_double(((long long)q_hi << 32) | (long long)q_lo);
                 for (int e = lane; e < dg_n; e += WAVE) {
                     const int pp = (int)st_n + e;
                     unsigned t;
@@ -679,7 +683,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             }
         }
         if (ltot > 0)
-            bld2_push_list<T>(Fl, Tg, tdelta, ncap, nloc, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start), sc_q,
+            bld2_push_list<double>(Fl, Tg, tdelta, ncap, nloc, a.loc_tgt, lb, reinterpret_cast<const int *>(sc_start), sc_q,
                               sc_bits, ltot, lane);
         if (!any) break;
     }
@@ -716,7 +720,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
             // the wave's 64 lanes hold 64 consecutive nodes starting at a multiple of 64
             const u64 bits = __ballot(i < cnt && sv[u] != (T)0);
             if (i < cnt) {
-                const T v = Fl[i];
+                const T v = (T)Fl[i];
                 F[base + i] = v;
                 if (rm[u]) Snext[base + i] = sv[u];
                 if ((threadIdx.x & (WAVE - 1)) == 0) Sbnext[(base + i) >> 6] = bits;

@@ -117,10 +117,10 @@ def reference_x(og, Z):
 @pytest.mark.parametrize("fp32", [False, True])
 @pytest.mark.parametrize("rb", [8, 0, 10, "max"])
 def test_block_local_solve(gpu, oracle_graphs, name, fp32, rb):
-    # rb "max" = the largest range (14 with float fluid, 13 with double): the kernel that
+    # rb "max" = the largest range (13, for either fluid type): the kernel that
     # reads the local adjacency from global memory; smaller ranges stage it in LDS
     if rb == "max":
-        rb = 14 if fp32 else 13
+        rb = 13
     g, og = GRAPHS[name], oracle_graphs[name]
     Z = O.uniform_Z(g.n)
     x = reference_x(og, Z)
