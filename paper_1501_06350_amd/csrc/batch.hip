@@ -88,6 +88,14 @@ struct BatchState {
     // exact per-column sums of H (mass balance): limb slots and k doubles
     u64 *partH = nullptr;
     double *hsum = nullptr;
+    // fluid recomputation: IN rows longer than REFINE_SEG entries are split into segments
+    // (segment s: row seg_row[s], entries [seg_p0[s], seg_p1[s])); a row's segments are
+    // consecutive and their partial sums (seg_part, nseg x KMAX) are added in order
+    i64 nseg = 0, nlong = 0;
+    int *seg_row = nullptr;
+    i64 *seg_p0 = nullptr, *seg_p1 = nullptr;
+    int *long_first = nullptr;  // nlong + 1: first segment of each long row
+    double *seg_part = nullptr;
 };
 
 struct TileArgs {
@@ -283,8 +291,9 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_push(TileArgs a) {
 //   3. writes its rows of F back and flags the rows whose S_i holds this sweep's fluid
 //      (one bit per row).
 // k_tile_deliver: one wave per unit of cross-range in-entries (whole target rows,
-//   or a segment of a long row) gathers the flagged in-flight rows, adds them up per
-//   target in registers and adds the sum to the target's fluid row.
+//   or a segment of a long row) lists the unit's flagged entries, gathers their
+//   in-flight rows, adds them up per target in registers and adds the sum to the
+//   target's fluid row.
 // No device-scope atomics on the common path: on this chip they are carried out past
 // the per-XCD L2 caches.  The residual of every column, |F|_1 plus the fluid in
 // flight, is summed at write-back; delivery moves fluid without changing it.
@@ -331,8 +340,8 @@ struct TileBldArgs {
 inline size_t tile_edge_bytes(bool weighted) { return weighted ? 6 : 2; }
 
 // LDS of a range (the edge buffer comes on top): the fluid tile (double), degrees and
-// local row offsets (u32), then per row the out-weight of its cross-range edges and, for
-// weighted graphs, 1/s_i (doubles, 8-byte aligned)
+// local row offsets (u32), then per row the out-weight of its cross-range edges and 1/s_i
+// (doubles, 8-byte aligned)
 __host__ __device__ inline size_t tile_rowdata_offset(int rb, int k) {
     const size_t B = (size_t)1 << rb;
     return (B * k * 8 + (2 * B + 1) * 4 + 7) & ~(size_t)7;
@@ -340,7 +349,8 @@ __host__ __device__ inline size_t tile_rowdata_offset(int rb, int k) {
 
 __host__ __device__ inline size_t tile_bld_fixed_lds(int rb, int k, bool weighted) {
     const size_t B = (size_t)1 << rb;
-    return tile_rowdata_offset(rb, k) + B * 8 * (weighted ? 2 : 1) + 16;
+    (void)weighted;
+    return tile_rowdata_offset(rb, k) + B * 16 + 16;
 }
 
 // two workgroups per compute unit when the tiles and 1024 local edges fit TB_LDS
@@ -424,7 +434,7 @@ __device__ __forceinline__ void tile_take_rows(const TileBldArgs &a, unsigned ac
             Ld += f;
             continue;
         }
-        const double q = (a.d * f) * (WTD ? Inv[i] : 1.0 / (double)deg);
+        const double q = (a.d * f) * Inv[i];
         if (dfl & 0x80000000u) {
             const T sv = (T)q;
             const unsigned bit = 1u << (ubase + u);
@@ -470,9 +480,9 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
     unsigned *Deg = reinterpret_cast<unsigned *>(Fl + (size_t)B * k);
     unsigned *Off = Deg + B;
     double *Rw = reinterpret_cast<double *>(smem + tile_rowdata_offset(a.rb, k));
-    double *Inv = Rw + B;  // weighted graphs only
+    double *Inv = Rw + B;
     // edge buffer: weights (4-byte aligned) first, then the 16-bit targets
-    float *Ew = reinterpret_cast<float *>(WTD ? Inv + B : Inv);
+    float *Ew = reinterpret_cast<float *>(Inv + B);
     unsigned short *Et = reinterpret_cast<unsigned short *>(WTD ? Ew + a.le_max : Ew);
     T *F = reinterpret_cast<T *>(a.F);
 
@@ -503,7 +513,7 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
             const unsigned dv = row ? a.deg_flags[base + i] : 0u;
             const i64 ov = offrow ? a.loc_ptr[base + i] : 0;
             const double rv = row ? a.rw[base + i] : 0.0;
-            const double iv = WTD && row ? a.inv_s[base + i] : 0.0;
+            const double iv = !row ? 0.0 : WTD ? a.inv_s[base + i] : (dv & 0x7fffffffu) ? 1.0 / (double)(dv & 0x7fffffffu) : 0.0;
             for (int e0 = threadIdx.x; e0 < nv; e0 += nthr * SU) {
                 uint4 v[SU];
 #pragma unroll
@@ -516,7 +526,7 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
             if (row) {
                 Deg[i] = dv;
                 Rw[i] = rv;
-                if (WTD) Inv[i] = iv;
+                Inv[i] = iv;
             }
             if (offrow) Off[i] = (unsigned)(ov - lb);
             if (lds_edges) {
@@ -616,66 +626,86 @@ struct TileDlArgs {
     u64 *partK;  // per-workgroup count of rows delivered
 };
 
+// The wave first works out, lane-parallel, which entries of its unit are flagged and
+// which flagged entry ends its target's run (no later flagged entry of the unit has the
+// same target: entries are sorted by target), and lists the flagged entries in LDS in
+// entry order; it then walks the list, gathering PB in-flight rows at a time.
+struct DlSlot {
+    int src, tgt, w, end;
+};
+
+__device__ __forceinline__ void dl_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, bool WTD>
 __global__ void __launch_bounds__(DL_THREADS) k_tile_deliver(TileDlArgs a) {
     __shared__ u64 kred[2 * DL_WAVES];
+    __shared__ DlSlot slots[DL_WAVES][WAVE];
     if (!a.force && tile_stopped(a.ctl)) return;
-    constexpr int PB = 16;  // in-flight rows gathered per batch
+    constexpr int PB = 8;  // in-flight rows gathered per batch
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
     const bool colk = lane < a.k;
     const int k = a.k;
     const T *S = reinterpret_cast<const T *>(a.S);
     T *F = reinterpret_cast<T *>(a.F);
+    DlSlot *sl = slots[w];
     u64 delivered = 0;
     const i64 nw = (i64)gridDim.x * DL_WAVES;
     for (i64 q = (i64)blockIdx.x * DL_WAVES + w; q < a.nunits; q += nw) {
         const DlUnit un = a.units[q];
+        const bool in = lane < un.len;
         const i64 p = un.e0 + min(lane, un.len - 1);
         const int src = a.rem_src[p];
         const int tgt = a.rem_tgt[p];
         const float ew = WTD ? a.rem_w[p] : 1.0f;
-        u64 m = __ballot(lane < un.len && ((a.fl[src >> 5] >> (src & 31)) & 1u));
-        delivered += lane == 0 ? (u64)__popcll(m) : 0ull;
+        const bool flg = in && ((a.fl[src >> 5] >> (src & 31)) & 1u);
+        const u64 m = __ballot(flg);
+        if (m == 0) continue;
+        const int nf = __popcll(m);
+        delivered += lane == 0 ? (u64)nf : 0ull;
+        // last entry of each target's segment, then: no flagged entry after this one up
+        // to the end of its segment
+        const int tnext = __shfl_down(tgt, 1);
+        const u64 seg_end = __ballot(in && (lane == un.len - 1 || tnext != tgt));
+        const u64 ge = seg_end & (~0ull << lane);
+        const int e = ge ? __ffsll((long long)ge) - 1 : WAVE - 1;
+        const u64 after = lane == WAVE - 1 ? 0ull : (~0ull << (lane + 1));
+        const u64 upto = e == WAVE - 1 ? ~0ull : ((1ull << (e + 1)) - 1);
+        const bool end = (m & after & upto) == 0;
+        const int pos = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (flg) sl[pos] = DlSlot{src, tgt, WTD ? __float_as_int(ew) : 0, end ? 1 : 0};
+        dl_wave_sync();
         T run = (T)0;
-        while (m) {
-            int bl[PB];
+        for (int b0 = 0; b0 < nf; b0 += PB) {
+            DlSlot d[PB];
 #pragma unroll
-            for (int u = 0; u < PB; ++u) {
-                bl[u] = m ? __ffsll((long long)m) - 1 : -1;
-                m &= m ? m - 1 : 0ull;
-            }
+            for (int u = 0; u < PB; ++u) d[u] = sl[min(b0 + u, nf - 1)];
             T sv[PB];
 #pragma unroll
-            for (int u = 0; u < PB; ++u) {
-                const int s = __builtin_amdgcn_readlane(src, bl[u] < 0 ? bl[0] : bl[u]);
-                const T *row = S + (i64)s * k;
-                sv[u] = colk ? row[lane] : (T)0;
-            }
+            for (int u = 0; u < PB; ++u) sv[u] = colk ? S[(i64)d[u].src * k + lane] : (T)0;
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
-                if (bl[u] < 0) break;
-                const int t = __builtin_amdgcn_readlane(tgt, bl[u]);
+                if (b0 + u >= nf) break;
                 T val = sv[u];
-                if (WTD)
-                    val = (T)((double)val * (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(ew), bl[u])));
+                if (WTD) val = (T)((double)val * (double)__int_as_float(d[u].w));
                 run += val;
-                // the run of target t ends at the last flagged entry of the unit, or
-                // where the next flagged entry has another target
-                const int nxt = u + 1 < PB ? bl[u + 1] : (m ? __ffsll((long long)m) - 1 : -1);
-                if (nxt < 0 || __builtin_amdgcn_readlane(tgt, nxt) != t) {
+                if (d[u].end) {
                     if (colk && run != (T)0) {
-                        if (un.split) atomicAdd(&F[(i64)t * k + lane], run);
-                        else F[(i64)t * k + lane] += run;
+                        if (un.split) atomicAdd(&F[(i64)d[u].tgt * k + lane], run);
+                        else F[(i64)d[u].tgt * k + lane] += run;
                     }
                     run = (T)0;
                 }
             }
         }
+        dl_wave_sync();  // the next unit reuses the list
     }
     u64 kv[2] = {0, delivered};
     block_store_partials<2>(kv, kred, a.partK + (i64)blockIdx.x * 2);
 }
-
 
 // Deterministic sweep, step 1: active entries of running columns move to H; snap holds
 // (d f) / s_i for them (0 elsewhere); dangling ones add to the leak.
@@ -749,38 +779,80 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_pull(TileArgs a) {
 
 // Fluid recomputation: F_jc = (F0_jc + d sum over IN row j of H_ic / s_i (* w)) - H_jc,
 // in double, stored in the fluid type.
+constexpr int REFINE_SEG = 2048;  // IN entries per segment of a long row
+
+// d-free part of the recomputation over IN entries [p0, p1): sum of H_ic / s_i (* w), in
+// entry order.  64 entries per step: lane l loads source l's index and scale; then
+// RF_U history rows are gathered at a time.
+constexpr int RF_U = 8;
+template <bool WTD>
+__device__ __forceinline__ double tile_in_sum(const TileArgs &a, i64 p0, i64 p1, int lane, bool col) {
+    double acc = 0.0;
+    for (i64 pb = p0; pb < p1; pb += WAVE) {
+        const int cnt = (int)min((i64)WAVE, p1 - pb);
+        const int mysrc = a.in_idx[pb + min(lane, cnt - 1)];
+        double mys = a.inv_s[mysrc];
+        if (WTD) mys *= (double)a.in_w[pb + min(lane, cnt - 1)];
+        for (int kb = 0; kb < cnt; kb += RF_U) {
+            double hv[RF_U], sv[RF_U];
+#pragma unroll
+            for (int u = 0; u < RF_U; ++u) {
+                const int kk = min(kb + u, cnt - 1);
+                const i64 src = __shfl(mysrc, kk, WAVE);
+                sv[u] = __shfl(mys, kk, WAVE);
+                hv[u] = col ? a.H[src * a.k + lane] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < RF_U; ++u)
+                if (kb + u < cnt) acc += hv[u] * sv[u];
+        }
+    }
+    return acc;
+}
+
+// Rows up to REFINE_SEG IN entries: each wave takes a contiguous block of rows (most
+// in-neighbours of a row sit in its host, so its gathers mostly hit its XCD's L2).  Then
+// the waves share the segments of the longer rows, whose partial sums go to seg_part.
 template <typename T, bool WTD>
-__global__ void __launch_bounds__(TILE_THREADS) k_tile_refine(TileArgs a, const double *F0) {
+__global__ void __launch_bounds__(TILE_THREADS) k_tile_refine(TileArgs a, const double *F0, const int *seg_row,
+                                                              const i64 *seg_p0, const i64 *seg_p1, i64 nseg,
+                                                              double *seg_part) {
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
     const bool col = lane < a.k;  // every lane takes part in the index loads and shuffles
     T *F = reinterpret_cast<T *>(a.F);
-    const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
-    for (i64 j = (i64)blockIdx.x * TILE_WAVES + w; j < a.n; j += nwaves) {
+    const i64 nwaves = (i64)gridDim.x * TILE_WAVES, gw = (i64)blockIdx.x * TILE_WAVES + w;
+    const i64 per = (a.n + nwaves - 1) / nwaves;
+    const i64 j0 = gw * per, j1 = min(a.n, j0 + per);
+    for (i64 j = j0; j < j1; ++j) {
         const i64 p0 = a.in_ptr[j], p1 = a.in_ptr[j + 1];
-        double acc = 0.0;
-        // 64 in-edges per step: lane l loads source l's index and scale 1/s (* w); then
-        // EDGES_U history rows are gathered at a time
-        for (i64 pb = p0; pb < p1; pb += WAVE) {
-            const int cnt = (int)min((i64)WAVE, p1 - pb);
-            const int mysrc = a.in_idx[pb + min(lane, cnt - 1)];
-            double mys = a.inv_s[mysrc];
-            if (WTD) mys *= (double)a.in_w[pb + min(lane, cnt - 1)];
-            for (int kb = 0; kb < cnt; kb += EDGES_U) {
-                double hv[EDGES_U], sv[EDGES_U];
-#pragma unroll
-                for (int u = 0; u < EDGES_U; ++u) {
-                    const int kk = min(kb + u, cnt - 1);
-                    const i64 src = __shfl(mysrc, kk, WAVE);
-                    sv[u] = __shfl(mys, kk, WAVE);
-                    hv[u] = col ? a.H[src * a.k + lane] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < EDGES_U; ++u)
-                    if (kb + u < cnt) acc += hv[u] * sv[u];
-            }
-        }
+        if (p1 - p0 > REFINE_SEG) continue;
+        const double acc = tile_in_sum<WTD>(a, p0, p1, lane, col);
         if (col) {
             const i64 slot = j * a.k + lane;
+            F[slot] = (T)((F0[slot] + a.d * acc) - a.H[slot]);
+        }
+    }
+    for (i64 sg = gw; sg < nseg; sg += nwaves) {
+        const double acc = tile_in_sum<WTD>(a, seg_p0[sg], seg_p1[sg], lane, col);
+        if (col) seg_part[sg * KMAX + lane] = acc;
+    }
+}
+
+// The long rows: their segments' partial sums, added in segment order.
+template <typename T>
+__global__ void __launch_bounds__(TILE_THREADS) k_tile_refine_long(TileArgs a, const double *F0, const int *seg_row,
+                                                                   const int *long_first, i64 nlong,
+                                                                   const double *seg_part) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+    const bool col = lane < a.k;
+    T *F = reinterpret_cast<T *>(a.F);
+    const i64 nwaves = (i64)gridDim.x * TILE_WAVES;
+    for (i64 q = (i64)blockIdx.x * TILE_WAVES + w; q < nlong; q += nwaves) {
+        const int s0 = long_first[q], s1 = long_first[q + 1];
+        double acc = 0.0;
+        for (int sg = s0; sg < s1; ++sg) acc += col ? seg_part[(i64)sg * KMAX + lane] : 0.0;
+        if (col) {
+            const i64 slot = (i64)seg_row[s0] * a.k + lane;
             F[slot] = (T)((F0[slot] + a.d * acc) - a.H[slot]);
         }
     }
@@ -1099,13 +1171,31 @@ constexpr double REFINE_MARGIN = 0.5;
 static int refine_tile(BatchState *b, const DevGraph &g, const SweepParams &p, hipStream_t st) {
     const TileArgs a = tile_args(b, g, p);
     if (b->fp32) {
-        if (g.weighted) k_tile_refine<float, true><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0);
-        else k_tile_refine<float, false><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0);
+        if (g.weighted)
+            k_tile_refine<float, true><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0, b->seg_row, b->seg_p0, b->seg_p1,
+                                                                       b->nseg, b->seg_part);
+        else
+            k_tile_refine<float, false><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0, b->seg_row, b->seg_p0, b->seg_p1,
+                                                                        b->nseg, b->seg_part);
     } else {
-        if (g.weighted) k_tile_refine<double, true><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0);
-        else k_tile_refine<double, false><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0);
+        if (g.weighted)
+            k_tile_refine<double, true><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0, b->seg_row, b->seg_p0, b->seg_p1,
+                                                                        b->nseg, b->seg_part);
+        else
+            k_tile_refine<double, false><<<b->gridP, TILE_THREADS, 0, st>>>(a, b->F0, b->seg_row, b->seg_p0, b->seg_p1,
+                                                                         b->nseg, b->seg_part);
     }
     DI_LAUNCH_CHECK();
+    if (b->nlong > 0) {
+        const int gl = (int)std::min<i64>(TILE_GRID, (b->nlong + TILE_WAVES - 1) / TILE_WAVES);
+        if (b->fp32)
+            k_tile_refine_long<float><<<gl, TILE_THREADS, 0, st>>>(a, b->F0, b->seg_row, b->long_first, b->nlong,
+                                                                   b->seg_part);
+        else
+            k_tile_refine_long<double><<<gl, TILE_THREADS, 0, st>>>(a, b->F0, b->seg_row, b->long_first, b->nlong,
+                                                                    b->seg_part);
+        DI_LAUNCH_CHECK();
+    }
     DI_TRY(launch_tile_reduce(b, a, 1, st));
     return launch_tile_finalize(b, p, FIN_INIT, b->gridR, 0, 0, st);
 }
@@ -1126,7 +1216,8 @@ void free_batch(BatchState *b) {
     if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
     void *ps[] = {b->F,   b->F0,      b->H,         b->snap,  b->ctl,         b->partR,
                   b->partC, b->partK, b->S,       b->fl,        b->blk_ptr, b->blk_ranges,
-                  b->units, b->rem_tgt_abs, b->partH, b->hsum};
+                  b->units, b->rem_tgt_abs, b->partH, b->hsum, b->seg_row, b->seg_p0, b->seg_p1,
+                  b->long_first, b->seg_part};
     for (void *q : ps)
         if (q) (void)hipFree(q);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
@@ -1260,6 +1351,41 @@ static int build_delivery_units(BatchState *b, const DevGraph &g) {
     return DI_OK;
 }
 
+// The recomputation's segments of the IN rows longer than REFINE_SEG entries.
+static int build_refine_segments(BatchState *b, const DevGraph &g) {
+    const i64 n = b->n;
+    std::vector<i64> ip((size_t)n + 1);
+    DI_HIP(hipMemcpy(ip.data(), g.in_ptr, sizeof(i64) * (n + 1), hipMemcpyDeviceToHost));
+    std::vector<int> srow, lfirst;
+    std::vector<i64> sp0, sp1;
+    for (i64 j = 0; j < n; ++j) {
+        if (ip[j + 1] - ip[j] <= REFINE_SEG) continue;
+        lfirst.push_back((int)srow.size());
+        for (i64 q = ip[j]; q < ip[j + 1]; q += REFINE_SEG) {
+            srow.push_back((int)j);
+            sp0.push_back(q);
+            sp1.push_back(std::min<i64>(q + REFINE_SEG, ip[j + 1]));
+        }
+    }
+    b->nseg = (i64)srow.size();
+    b->nlong = (i64)lfirst.size();
+    lfirst.push_back((int)srow.size());
+    if (b->nseg == 0) return DI_OK;
+    if (hipMalloc((void **)&b->seg_row, sizeof(int) * srow.size()) != hipSuccess ||
+        hipMalloc((void **)&b->seg_p0, 8 * sp0.size()) != hipSuccess ||
+        hipMalloc((void **)&b->seg_p1, 8 * sp1.size()) != hipSuccess ||
+        hipMalloc((void **)&b->long_first, 4 * lfirst.size()) != hipSuccess ||
+        hipMalloc((void **)&b->seg_part, 8 * (size_t)KMAX * srow.size()) != hipSuccess) {
+        set_error("device allocation of the recomputation segments failed");
+        return DI_ENOMEM;
+    }
+    DI_HIP(hipMemcpy(b->seg_row, srow.data(), sizeof(int) * srow.size(), hipMemcpyHostToDevice));
+    DI_HIP(hipMemcpy(b->seg_p0, sp0.data(), 8 * sp0.size(), hipMemcpyHostToDevice));
+    DI_HIP(hipMemcpy(b->seg_p1, sp1.data(), 8 * sp1.size(), hipMemcpyHostToDevice));
+    DI_HIP(hipMemcpy(b->long_first, lfirst.data(), 4 * lfirst.size(), hipMemcpyHostToDevice));
+    return DI_OK;
+}
+
 int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int det, const double *Z,
                const int *range_order, int rounds, hipStream_t st) {
     bout = nullptr;
@@ -1310,6 +1436,10 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
         !alloc((void **)&b->partH, (size_t)b->gridR * KMAX * 4 * 8) || !alloc((void **)&b->hsum, 2 * KMAX * 8) ||
         (det && !alloc((void **)&b->snap, n * k * 8)))
         return fail(DI_ENOMEM);
+    if (p.fp32 && !det) {
+        const int src = build_refine_segments(b, g);
+        if (src != DI_OK) return fail(src);
+    }
     if (b->bld) {
         if (!alloc(&b->S, n * k * T) || !alloc((void **)&b->fl, (size_t)((n + 31) / 32) * 4) ||
             !alloc((void **)&b->blk_ptr, (size_t)(b->gridB + 1) * 4) ||

@@ -48,6 +48,21 @@ def rand_weighted(n, seed):
     return W.from_edges(n, src, dst, w, "rand%d" % n)
 
 
+def hub_graph(n, seed, weighted):
+    """Random sparse graph plus three hubs with 2500-5000 in-edges each (IN rows longer
+    than one segment of the float tile's fluid recomputation)."""
+    rng = np.random.default_rng(seed)
+    deg = rng.integers(0, 6, size=n)
+    src = [np.repeat(np.arange(n), deg)]
+    dst = [rng.integers(0, n, size=int(deg.sum()))]
+    for hub, cnt in ((3, 5000), (n // 2, 2600), (n - 5, 4100)):
+        src.append(rng.choice(n, size=cnt, replace=False))
+        dst.append(np.full(cnt, hub))
+    src, dst = np.concatenate(src), np.concatenate(dst)
+    w = rng.lognormal(0, 1, size=len(src)).astype(np.float32) if weighted else None
+    return W.from_edges(n, src, dst, w, "hubs%d" % n)
+
+
 # ---------------------------------------------------------------------------
 # n x k tile
 # ---------------------------------------------------------------------------
@@ -80,9 +95,15 @@ def test_tile_deterministic_bit_exact(gpu, case):
     assert st["sweeps"] == done.max()
 
 
-@pytest.mark.parametrize("case", ["rand1500_w_f64", "rand1500_w_f32", "web50k_f32", "web50k_f64"])
+@pytest.mark.parametrize("case", ["rand1500_w_f64", "rand1500_w_f32", "web50k_f32", "web50k_f64", "hubs6k_f32",
+                                  "hubs6k_w_f32"])
 def test_tile_fast_certificates(gpu, case):
-    g = rand_weighted(1500, 9) if case.startswith("rand") else W.webgen(50_000, 6)
+    if case.startswith("rand"):
+        g = rand_weighted(1500, 9)
+    elif case.startswith("hubs"):
+        g = hub_graph(6000, 12, "_w_" in case)
+    else:
+        g = W.webgen(50_000, 6)
     fp32 = case.endswith("f32")
     k = 64
     og = O.OGraph.of(g)
