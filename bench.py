@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner: the headline uses --theta and --rounds as given")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: the user's cache dir)")
+    ap.add_argument("--no-heldout", action="store_true",
+                    help="skip the autotuner check on a graph of another seed (webgen(n, seed 7))")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a copy of known size, then one DI solve")
     ap.add_argument("--curves", action="store_true",
@@ -300,6 +302,13 @@ def main():
             result["update_50m"] = {"error": str(e)[:300]}
         log("update_50m: %s" % json.dumps(result["update_50m"]))
 
+    if not args.no_heldout and not args.no_tune:
+        try:
+            result["autotuner_heldout"] = bench_heldout(args, fp32, g)
+        except Exception as e:  # reported, not fatal
+            result["autotuner_heldout"] = {"error": str(e)[:300]}
+        log("autotuner_heldout: %s" % json.dumps(result["autotuner_heldout"]))
+
     if not args.no_batched:
         for key, fn in (("batched_k64", lambda: bench_batched(True)), ("union_256", bench_union),
                         ("adjoint_2m", bench_adjoint)):
@@ -318,6 +327,43 @@ def main():
             result["di_deterministic"] = {"error": str(e)[:300]}
         result["cpu_baseline"] = cpu_baseline(g, pi["iterations"], args.cpu_pi_iters, args.cpu_sweeps, det)
     print(json.dumps(result), flush=True)
+
+
+def bench_heldout(args, fp32, g_head, seed=7):
+    """The autotuner on a graph of another seed, webgen(n, 7): the hand-tuned options of the
+    headline (--theta, --rounds) and a fresh search of the tuner on this graph, each timed
+    as the median of three solves; plus whether its degree-structure hash equals the
+    headline graph's, i.e. whether a cached choice would carry over between the two."""
+    import tempfile
+    import workloads as W
+    from paper_1501_06350_amd import binding as B
+    from paper_1501_06350_amd import tune
+    g = W.webgen(args.n, seed)
+    key = tune.graph_key(g, 1, fp32, D, TOL)
+    head_key = tune.graph_key(g_head, 1, fp32, D, TOL)
+    fd, cache = tempfile.mkstemp(suffix=".json")
+    os.close(fd)
+    os.unlink(cache)
+    try:
+        s = B.from_graph(g, d=D, fluid_fp32=fp32, timing=True, range_log2=args.range_log2, inner_rounds=args.rounds,
+                         theta=args.theta, range_cut=args.range_cut)
+        tuner = tune.Tuner(cache, log=log)
+        tuner._time(s, TOL)  # warm-up
+        hand = statistics.median([tuner._time(s, TOL) for _ in range(3)])
+        t0 = time.time()
+        res = tuner.tune_context(s, key, TOL, force=True)
+        secs = time.time() - t0
+        tuned = statistics.median([tuner._time(s, TOL) for _ in range(3)])
+        s.close()
+    finally:
+        if os.path.exists(cache):
+            os.unlink(cache)
+    return {"workload": "webgen n=%d m=%d seed=%d" % (g.n, g.m, seed),
+            "hand_tuned": {"theta": args.theta, "inner_rounds": args.rounds, "ms": round(hand, 3)},
+            "tuned": {"theta": res["theta"], "inner_rounds": res["inner_rounds"], "ms": round(tuned, 3),
+                      "search_seconds": round(secs, 1)},
+            "tuned_over_hand": round(tuned / hand, 4),
+            "degree_hash_matches_headline_graph": key.split(" deg=")[1] == head_key.split(" deg=")[1]}
 
 
 COPY_BYTES = 1 << 30

@@ -1164,7 +1164,7 @@ static int enqueue_tile_sweep(BatchState *b, const DevGraph &g, const SweepParam
 constexpr double REFINE_DROP = 0x1p-14;
 // while the fluid is float, sweeps aim at REFINE_MARGIN * tol so that the residual of
 // the recomputed fluid (the float pushes' rounding added back) still meets tol
-constexpr double REFINE_MARGIN = 0.5;
+constexpr double REFINE_MARGIN = 0.8;
 
 // Recompute the fluid (see above), then every column's residual, stop and threshold
 // under the tolerance in p.

@@ -241,7 +241,7 @@ int reset_state(di_ctx *c) {
 constexpr double REFINE_DROP = 0x1p-14;
 // while the fluid is float, sweeps aim at REFINE_MARGIN * tol so that the residual of
 // the recomputed fluid (the float pushes' rounding added back) still meets tol
-constexpr double REFINE_MARGIN = 0.5;
+constexpr double REFINE_MARGIN = 0.8;
 // share of the cross-range entries that must carry fluid in a block-local sweep for the
 // next one to read the in-flight values without testing the bitmap (on the 50M web graph
 // the direct reads win at about 0.6 of the entries live, the bitmap at about 0.4)
