@@ -162,6 +162,11 @@ def main():
     ap.add_argument("--curve-rounds", type=int, default=60)
     ap.add_argument("--batched-only", action="store_true",
                     help="for profiling: run only the k=64, 256-graph and adjoint legs and print their figures")
+    ap.add_argument("--tile-only", action="store_true",
+                    help="for profiling: only the k=64 tile solve with --tile-theta / --tile-rounds, stream and "
+                         "graph loop modes")
+    ap.add_argument("--tile-theta", type=float, default=1.0)
+    ap.add_argument("--tile-rounds", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU partitioning of the sweep is a design "
@@ -181,6 +186,9 @@ def main():
         return
     if args.curves:
         print(json.dumps({"convergence": cpu_baseline_curves(args.curve_rounds, args.theta, args.rounds)}), flush=True)
+        return
+    if args.tile_only:
+        print(json.dumps({"tile": bench_tile_only(args.tile_theta, args.tile_rounds)}), flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched": bench_batched(True), "union": bench_union(), "adjoint": bench_adjoint()}),
@@ -442,7 +450,7 @@ def _timed(fn):
 def bench_batched(fp32):
     """Personalized PageRank, webgen(4M, seed 4), k=64 columns of 16 seeds each, L1 tol 1e-8
     per column: one k=64 tile solve (float fluid, the tile's precision, theta and rounds from
-    the autotuner) vs 64 single-column solves on the same resident graph (di_set_z between them,
+    the autotuner, HIP-graph loop mode) vs 64 single-column solves on the same resident graph (di_set_z between them,
     outside the timed calls) in float and double fluid with (theta, rounds) = (1, 4), (0.5, 4)
     and (0.2, 6); the speedup is taken against the fastest of the six."""
     import numpy as np
@@ -475,8 +483,10 @@ def bench_batched(fp32):
     t0 = time.time()
     tt = tune.Tuner(None, log=log).tune_tile(g, Z, D, TOL, fluid_fp32=fp32)
     out["tile_autotuner"] = dict(tt, seconds=round(time.time() - t0, 1))
-    with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=fp32, theta=tt["theta"], inner_rounds=tt["inner_rounds"]) as sb:
-        sb.diffuse(TOL)  # warm-up
+    # the sweeps run as captured chunks replayed as HIP graphs (one launch per chunk)
+    with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=fp32, theta=tt["theta"], inner_rounds=tt["inner_rounds"],
+                      loop_mode=B.LOOP_GRAPH) as sb:
+        sb.diffuse(TOL)  # warm-up and capture
         sb.reset()
         st, ms = _timed(lambda: sb.diffuse(TOL))
         assert st["converged"]
@@ -493,6 +503,31 @@ def bench_batched(fp32):
     alg = st["edge_updates"] * (4 + 2 * k * T) / k + st["node_updates"] * k * (2 * T + 16) + \
         st["sweeps"] * g.n * k * T
     out["roofline"] = roofline(alg / (ms * 1e-3) / 1e9, scope="whole k=64 solve")
+    return out
+
+
+def bench_tile_only(theta, rounds):
+    """The k=64 float tile of bench_batched alone, with fixed options, in both loop modes
+    (sweeps launched from the host, or captured chunks replayed as HIP graphs)."""
+    import numpy as np
+    import workloads as W
+    from paper_1501_06350_amd import binding as B
+    g = W.webgen(4_000_000, 4)
+    Z = W.ppr_Z(g.n, 64, 16, 4)
+    out = {"workload": "webgen n=%d m=%d seed=4, k=64 x 16 seeds, f32 fluid tile" % (g.n, g.m),
+           "theta": theta, "inner_rounds": rounds}
+    for mode, name in ((B.LOOP_STREAM, "stream"), (B.LOOP_GRAPH, "graph")):
+        with B.from_graph(g, d=D, Z=Z, k=64, fluid_fp32=True, theta=theta, inner_rounds=rounds,
+                          loop_mode=mode) as sb:
+            sb.diffuse(TOL)  # warm-up (and, in graph mode, the capture)
+            best = None
+            for _ in range(3):
+                sb.reset()
+                st, ms = _timed(lambda: sb.diffuse(TOL))
+                assert st["converged"]
+                best = ms if best is None else min(best, ms)
+        out[name] = {"ms": round(best, 3), "sweeps": st["sweeps"], "bound": st["bound"]}
+        log("tile (%s loop): %.2f ms, %d sweeps" % (name, best, st["sweeps"]))
     return out
 
 

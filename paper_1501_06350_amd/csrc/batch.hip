@@ -76,6 +76,7 @@ struct BatchState {
     hipStream_t cap_st = nullptr;
     hipGraphExec_t gexec = nullptr;
     int gexec_spc = 0;
+    double gexec_tol = -1.0, gexec_theta = -1.0;  // the sweeps' tolerance and threshold scale baked in
     // block-local sweeps
     int bld = 0, rounds = 4, gridB = 0, gridD = 0;
     void *S = nullptr;           // in-flight rows (n x k)
@@ -1492,7 +1493,7 @@ static int enqueue_tile_chunk(BatchState *b, const DevGraph &g, const SweepParam
         for (int s = 0; s < spc; ++s) DI_TRY(enqueue_tile_sweep(b, g, p, st));
         return DI_OK;
     }
-    if (!b->gexec || b->gexec_spc != spc) {
+    if (!b->gexec || b->gexec_spc != spc || b->gexec_tol != p.tol || b->gexec_theta != p.theta) {
         if (b->gexec) {
             (void)hipGraphExecDestroy(b->gexec);
             b->gexec = nullptr;
@@ -1515,6 +1516,8 @@ static int enqueue_tile_chunk(BatchState *b, const DevGraph &g, const SweepParam
             return DI_EHIP;
         }
         b->gexec_spc = spc;
+        b->gexec_tol = p.tol;
+        b->gexec_theta = p.theta;
     }
     DI_HIP(hipGraphLaunch(b->gexec, st));
     return DI_OK;
@@ -1522,10 +1525,6 @@ static int enqueue_tile_chunk(BatchState *b, const DevGraph &g, const SweepParam
 
 int diffuse_batch(BatchState *b, const DevGraph &g, const SweepParams &p, const di_opts &o, int spc,
                   hipStream_t st, di_stats *stats) {
-    if (b->gexec) {  // the tolerance is baked into a captured chunk
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-    }
     DI_HIP(hipEventRecord(b->ev0, st));
     // state of every column under this call's tolerance
     k_tile_begin<<<1, 1, 0, st>>>(b->ctl, (long long)o.max_sweeps);

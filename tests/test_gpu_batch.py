@@ -432,3 +432,14 @@ def test_graph_loop_mode_fast_batched(gpu, kind):
                     h = H[q] if kind == "tile" else H[gp[q]:gp[q + 1]]
                     assert np.abs(h - xr).sum() <= R[q] / (1 - D) * (1 + 1e-6) + 1e-13, (lm, rep, q)
                 s.read(gpu.X_NORM)  # eager work between replays
+            # new options and a new tolerance: the captured chunks must not be reused
+            s.reset()
+            s.set_options(theta=0.5, inner_rounds=3)
+            st = s.diffuse(1e-10)
+            assert st["converged"], lm
+            H = s.read(gpu.H)
+            R = s.read(gpu.RESIDUALS)
+            assert R.max() / (1 - D) <= 1e-10
+            for q, xr in enumerate(refs):
+                h = H[q] if kind == "tile" else H[gp[q]:gp[q + 1]]
+                assert np.abs(h - xr).sum() <= R[q] / (1 - D) * (1 + 1e-6) + 1e-13, (lm, "new options", q)
