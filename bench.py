@@ -86,8 +86,14 @@ def time_di(s, steps, warmup, n, m):
 
 
 def sweep_roofline(r, kernel, traffic=None):
-    """roofline object of the block-local sweep kernel from time_di's figures"""
-    return roofline(r["achieved"], traffic=traffic, kernel=kernel, launches=r["kern_launch"],
+    """roofline object of the block-local sweep kernel from time_di's figures; with the
+    counter-measured traffic per launch, also the rate and fraction of peak it implies at
+    this run's average launch duration"""
+    extra = {}
+    if traffic:
+        t_ach = traffic / r["avg_ns"]  # bytes per ns = GB/s
+        extra = {"traffic_achieved": round(t_ach, 1), "traffic_frac": round(t_ach / HBM_PEAK_GBS, 4)}
+    return roofline(r["achieved"], traffic=traffic, kernel=kernel, launches=r["kern_launch"], **extra,
                     avg_us=round(r["avg_ns"] / 1e3, 2), bytes_per_launch=round(r["bytes_per_launch"]),
                     model="push sweep: 4+2T B per edge update, 28+2T B per diffusion, T*n B per sweep",
                     design_model={"bytes_per_launch": round(r["design_bytes_per_launch"]),
@@ -419,7 +425,8 @@ def measured_traffic(prec, theta, range_cut, rounds):
 
 def traffic_probe(args, fp32):
     """Three copies of a known size (the counter scale), then one D-Iteration solve on the
-    headline graph; run under rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE."""
+    headline graph, then one power-iteration solve; run under rocprofv3 --pmc FETCH_SIZE,
+    then --pmc WRITE_SIZE."""
     import torch
     import workloads as W
     from paper_1501_06350_amd import binding as B
@@ -436,6 +443,11 @@ def traffic_probe(args, fp32):
     torch.cuda.synchronize()
     log("traffic probe: copies of %d bytes, then %d sweeps, source sha256 %s, options %s" %
         (COPY_BYTES, st["sweeps"], sweep_source_hash(), traffic_options(args.theta, args.range_cut, rounds)))
+    # then the comparator: power iteration with double x/s on the caller's numbering
+    with B.from_graph(g, d=D, fluid_fp32=False, range_cut=-1) as s:
+        p = s.power(TOL)
+    torch.cuda.synchronize()
+    log("traffic probe: then %d power iterations" % p["sweeps"])
 
 
 def _timed(fn):
