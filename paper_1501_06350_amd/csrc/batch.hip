@@ -59,6 +59,12 @@ struct DlUnit {
     int len, split;
 };
 
+// A range as the tile sweep visits it: first row, first local edge, rows, local edges.
+struct TileRange {
+    i64 base, lb;
+    int cnt, ne;
+};
+
 struct BatchState {
     int k = 0, fp32 = 0, K = 0, det = 0;
     i64 n = 0;
@@ -83,6 +89,7 @@ struct BatchState {
     unsigned *fl = nullptr;      // (n + 31) / 32 words: bit i, row i of S holds this sweep's fluid
     int *blk_ptr = nullptr;      // gridB + 1: each workgroup's share of blk_ranges
     int *blk_ranges = nullptr;   // nranges: ranges grouped by workgroup
+    TileRange *rinfo = nullptr;  // nranges: the ranges of blk_ranges, in the same order
     DlUnit *units = nullptr;     // delivery units over the cross-range in-entries
     i64 nunits = 0;
     int *rem_tgt_abs = nullptr;  // m_rem: absolute target row of each cross-range entry
@@ -326,6 +333,7 @@ struct TileBldArgs {
     const unsigned *deg_flags;
     const double *inv_s;
     const int *blk_ptr, *blk_ranges;
+    const TileRange *rinfo;  // per entry of blk_ranges: the range's first row, rows, local edges
     i64 n, nranges;
     int rb, k, K, rounds;
     int le_max;  // local edges of a range that fit the LDS edge buffer
@@ -494,65 +502,78 @@ __global__ void __launch_bounds__(TB_MAX_THREADS) k_tile_bld(TileBldArgs a) {
     double Rd = 0.0, Ld = 0.0;
     u64 mx = 0, nodes = 0, edges = 0;
     int bad = 0;
-    for (int q = a.blk_ptr[blockIdx.x]; q < a.blk_ptr[blockIdx.x + 1]; ++q) {
-        const int r = a.blk_ranges[q];
-        const i64 base = (i64)r << a.rb;
-        const int cnt = (int)min((i64)B, a.n - base);
-        const i64 lb = a.loc_base[r];
-        const int ne = (int)(a.loc_ptr[base + cnt] - lb);
+    // The next range's fluid (PF 16-byte units per thread), row data (B <= threads) and
+    // first PE local edges per thread are loaded into registers while the current range
+    // runs its local rounds; staging then stores registers (the rest, if any, is loaded
+    // at staging).
+    constexpr int VE = 16 / (int)sizeof(T), PF = 4, PE = 2;
+    uint4 pf[PF];
+    unsigned pdv = 0;
+    i64 pov = 0;
+    double prv = 0.0, piv = 0.0;
+    unsigned short pt[PE];
+    float pw[PE];
+    const int tid = threadIdx.x;
+    auto prefetch = [&](const TileRange &ri) {
+        const int tot = ri.cnt * k, nv = tot / VE;
+        const uint4 *srcv = reinterpret_cast<const uint4 *>(F + ri.base * k);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) pf[u] = nv > 0 ? srcv[min(tid + u * nthr, nv - 1)] : make_uint4(0, 0, 0, 0);
+        const bool row = tid < ri.cnt, offrow = tid <= ri.cnt;
+        pdv = row ? a.deg_flags[ri.base + tid] : 0u;
+        pov = offrow ? a.loc_ptr[ri.base + tid] : 0;
+        prv = row ? a.rw[ri.base + tid] : 0.0;
+        piv = WTD && row ? a.inv_s[ri.base + tid] : 0.0;
+        const bool le = ri.ne > 0 && ri.ne <= a.le_max;
+#pragma unroll
+        for (int u = 0; u < PE; ++u) {
+            const i64 e = ri.lb + min(tid + u * nthr, max(ri.ne - 1, 0));
+            pt[u] = le ? a.loc_tgt[e] : (unsigned short)0;
+            pw[u] = WTD && le ? a.loc_w[e] : 0.0f;
+        }
+    };
+    const int q0 = a.blk_ptr[blockIdx.x], q1 = a.blk_ptr[blockIdx.x + 1];
+    if (q0 < q1) prefetch(a.rinfo[q0]);
+    for (int q = q0; q < q1; ++q) {
+        const TileRange ri = a.rinfo[q];
+        const i64 base = ri.base, lb = ri.lb;
+        const int cnt = ri.cnt, ne = ri.ne;
         const bool lds_edges = ne <= a.le_max;
         // 1. stage: the range's fluid rows are one contiguous block of cnt * k values
-        // (256-byte aligned: ranges start at multiples of 64 rows), read in 16-byte units;
-        // each thread issues its loads of fluid, row data (B <= threads) and local edges
-        // before it stores any, so that their memory trips overlap
+        // (256-byte aligned: ranges start at multiples of 64 rows) in 16-byte units, the
+        // row data and the local edges, from the prefetched registers where they cover them
         {
-            constexpr int VE = 16 / (int)sizeof(T), SU = 8;
             const int tot = cnt * k, nv = tot / VE;
             const uint4 *srcv = reinterpret_cast<const uint4 *>(F + base * k);
-            const int i = threadIdx.x;
-            const bool row = i < cnt, offrow = i <= cnt;
-            const unsigned dv = row ? a.deg_flags[base + i] : 0u;
-            const i64 ov = offrow ? a.loc_ptr[base + i] : 0;
-            const double rv = row ? a.rw[base + i] : 0.0;
-            const double iv = !row ? 0.0 : WTD ? a.inv_s[base + i] : (dv & 0x7fffffffu) ? 1.0 / (double)(dv & 0x7fffffffu) : 0.0;
-            for (int e0 = threadIdx.x; e0 < nv; e0 += nthr * SU) {
-                uint4 v[SU];
 #pragma unroll
-                for (int u = 0; u < SU; ++u) v[u] = srcv[min(e0 + u * nthr, nv - 1)];
-#pragma unroll
-                for (int u = 0; u < SU; ++u)
-                    if (e0 + u * nthr < nv) tile_lds_unit<T>(Fl + (size_t)(e0 + u * nthr) * VE, v[u]);
+            for (int u = 0; u < PF; ++u)
+                if (tid + u * nthr < nv) tile_lds_unit<T>(Fl + (size_t)(tid + u * nthr) * VE, pf[u]);
+            for (int e = tid + PF * nthr; e < nv; e += nthr) tile_lds_unit<T>(Fl + (size_t)e * VE, srcv[e]);
+            for (int e = nv * VE + tid; e < tot; e += nthr) Fl[e] = (double)F[base * k + e];
+            if (tid < cnt) {
+                Deg[tid] = pdv;
+                Rw[tid] = prv;
+                const unsigned dg = pdv & 0x7fffffffu;
+                Inv[tid] = WTD ? piv : dg ? 1.0 / (double)dg : 0.0;
             }
-            for (int e = nv * VE + threadIdx.x; e < tot; e += nthr) Fl[e] = (double)F[base * k + e];
-            if (row) {
-                Deg[i] = dv;
-                Rw[i] = rv;
-                Inv[i] = iv;
-            }
-            if (offrow) Off[i] = (unsigned)(ov - lb);
+            if (tid <= cnt) Off[tid] = (unsigned)(pov - lb);
             if (lds_edges) {
-                constexpr int EU = 8;
-                for (int e0 = threadIdx.x; e0 < ne; e0 += nthr * EU) {
-                    unsigned short tv[EU];
-                    float wv[EU];
 #pragma unroll
-                    for (int u = 0; u < EU; ++u) {
-                        const int e = min(e0 + u * nthr, ne - 1);
-                        tv[u] = a.loc_tgt[lb + e];
-                        wv[u] = WTD ? a.loc_w[lb + e] : 0.0f;
+                for (int u = 0; u < PE; ++u) {
+                    const int e = tid + u * nthr;
+                    if (e < ne) {
+                        Et[e] = pt[u];
+                        if (WTD) Ew[e] = pw[u];
                     }
-#pragma unroll
-                    for (int u = 0; u < EU; ++u) {
-                        const int e = e0 + u * nthr;
-                        if (e < ne) {
-                            Et[e] = tv[u];
-                            if (WTD) Ew[e] = wv[u];
-                        }
-                    }
+                }
+                for (int e = tid + PE * nthr; e < ne; e += nthr) {
+                    Et[e] = a.loc_tgt[lb + e];
+                    if (WTD) Ew[e] = a.loc_w[lb + e];
                 }
             }
         }
         block_sync_lds();
+        if (q + 1 < q1) prefetch(a.rinfo[q + 1]);
         // 2. local rounds over the wave's rows [my0, my1), scanned RU at a time: their LDS
         // values are read before any is taken
         const int my0 = min(cnt, w * TB_RPW), my1 = min(cnt, my0 + TB_RPW);
@@ -1046,6 +1067,7 @@ static TileBldArgs tile_bld_args(BatchState *b, const DevGraph &g, const SweepPa
     a.inv_s = g.inv_s;
     a.blk_ptr = b->blk_ptr;
     a.blk_ranges = b->blk_ranges;
+    a.rinfo = b->rinfo;
     a.n = b->n;
     a.nranges = g.nranges;
     a.rb = g.rb;
@@ -1217,7 +1239,7 @@ void free_batch(BatchState *b) {
     if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
     void *ps[] = {b->F,   b->F0,      b->H,         b->snap,  b->ctl,         b->partR,
                   b->partC, b->partK, b->S,       b->fl,        b->blk_ptr, b->blk_ranges,
-                  b->units, b->rem_tgt_abs, b->partH, b->hsum, b->seg_row, b->seg_p0, b->seg_p1,
+                  b->units, b->rem_tgt_abs, b->partH, b->hsum, b->rinfo, b->seg_row, b->seg_p0, b->seg_p1,
                   b->long_first, b->seg_part};
     for (void *q : ps)
         if (q) (void)hipFree(q);
@@ -1303,6 +1325,13 @@ static int assign_ranges(BatchState *b, const DevGraph &g) {
     }
     DI_HIP(hipMemcpy(b->blk_ptr, ptr.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice));
     DI_HIP(hipMemcpy(b->blk_ranges, flat.data(), sizeof(int) * nr, hipMemcpyHostToDevice));
+    std::vector<TileRange> info((size_t)nr);
+    for (i64 q = 0; q < nr; ++q) {
+        const i64 r = flat[q], base = r << g.rb;
+        info[q] = TileRange{base, lbase[r], (int)std::min<i64>((i64)1 << g.rb, g.n - base),
+                            (int)(lbase[r + 1] - lbase[r])};
+    }
+    DI_HIP(hipMemcpy(b->rinfo, info.data(), sizeof(TileRange) * nr, hipMemcpyHostToDevice));
     return DI_OK;
 }
 
@@ -1444,7 +1473,8 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
     if (b->bld) {
         if (!alloc(&b->S, n * k * T) || !alloc((void **)&b->fl, (size_t)((n + 31) / 32) * 4) ||
             !alloc((void **)&b->blk_ptr, (size_t)(b->gridB + 1) * 4) ||
-            !alloc((void **)&b->blk_ranges, (size_t)g.nranges * 4))
+            !alloc((void **)&b->blk_ranges, (size_t)g.nranges * 4) ||
+            !alloc((void **)&b->rinfo, (size_t)g.nranges * sizeof(TileRange)))
             return fail(DI_ENOMEM);
         int src = assign_ranges(b, g);
         if (src == DI_OK) src = build_delivery_units(b, g);
