@@ -705,9 +705,15 @@ __global__ void __launch_bounds__(DL_THREADS) k_tile_deliver(TileDlArgs a) {
             DlSlot d[PB];
 #pragma unroll
             for (int u = 0; u < PB; ++u) d[u] = sl[min(b0 + u, nf - 1)];
-            T sv[PB];
+            // the in-flight rows, and the fluid rows of the targets whose run ends in this
+            // batch (no other wave writes them: a unit holds whole target rows, and the
+            // split units of a long row only add atomically)
+            T sv[PB], fv[PB];
 #pragma unroll
-            for (int u = 0; u < PB; ++u) sv[u] = colk ? S[(i64)d[u].src * k + lane] : (T)0;
+            for (int u = 0; u < PB; ++u) {
+                sv[u] = colk ? S[(i64)d[u].src * k + lane] : (T)0;
+                fv[u] = colk && d[u].end && !un.split ? F[(i64)d[u].tgt * k + lane] : (T)0;
+            }
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
                 if (b0 + u >= nf) break;
@@ -717,7 +723,7 @@ __global__ void __launch_bounds__(DL_THREADS) k_tile_deliver(TileDlArgs a) {
                 if (d[u].end) {
                     if (colk && run != (T)0) {
                         if (un.split) atomicAdd(&F[(i64)d[u].tgt * k + lane], run);
-                        else F[(i64)d[u].tgt * k + lane] += run;
+                        else F[(i64)d[u].tgt * k + lane] = fv[u] + run;
                     }
                     run = (T)0;
                 }
