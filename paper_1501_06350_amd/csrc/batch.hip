@@ -838,9 +838,10 @@ __device__ __forceinline__ double tile_in_sum(const TileArgs &a, i64 p0, i64 p1,
     return acc;
 }
 
-// Rows up to REFINE_SEG IN entries: each wave takes a contiguous block of rows (most
-// in-neighbours of a row sit in its host, so its gathers mostly hit its XCD's L2).  Then
-// the waves share the segments of the longer rows, whose partial sums go to seg_part.
+// Rows up to REFINE_SEG IN entries, consecutive rows on consecutive waves (the chip works
+// on a window of a few hosts at a time, whose history rows the L2 caches share; a
+// contiguous block of rows per wave measured 10% slower).  Then the waves share the
+// segments of the longer rows, whose partial sums go to seg_part.
 template <typename T, bool WTD>
 __global__ void __launch_bounds__(TILE_THREADS) k_tile_refine(TileArgs a, const double *F0, const int *seg_row,
                                                               const i64 *seg_p0, const i64 *seg_p1, i64 nseg,
@@ -849,9 +850,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile_refine(TileArgs a, const 
     const bool col = lane < a.k;  // every lane takes part in the index loads and shuffles
     T *F = reinterpret_cast<T *>(a.F);
     const i64 nwaves = (i64)gridDim.x * TILE_WAVES, gw = (i64)blockIdx.x * TILE_WAVES + w;
-    const i64 per = (a.n + nwaves - 1) / nwaves;
-    const i64 j0 = gw * per, j1 = min(a.n, j0 + per);
-    for (i64 j = j0; j < j1; ++j) {
+    for (i64 j = gw; j < a.n; j += nwaves) {
         const i64 p0 = a.in_ptr[j], p1 = a.in_ptr[j + 1];
         if (p1 - p0 > REFINE_SEG) continue;
         const double acc = tile_in_sum<WTD>(a, p0, p1, lane, col);
