@@ -87,9 +87,8 @@ struct BatchState {
     int bld = 0, rounds = 4, gridB = 0, gridD = 0;
     void *S = nullptr;           // in-flight rows (n x k)
     unsigned *fl = nullptr;      // (n + 31) / 32 words: bit i, row i of S holds this sweep's fluid
-    int *blk_ptr = nullptr;      // gridB + 1: each workgroup's share of blk_ranges
-    int *blk_ranges = nullptr;   // nranges: ranges grouped by workgroup
-    TileRange *rinfo = nullptr;  // nranges: the ranges of blk_ranges, in the same order
+    int *blk_ptr = nullptr;      // gridB + 1: each workgroup's share of rinfo
+    TileRange *rinfo = nullptr;  // nranges: the ranges, grouped by workgroup
     DlUnit *units = nullptr;     // delivery units over the cross-range in-entries
     i64 nunits = 0;
     int *rem_tgt_abs = nullptr;  // m_rem: absolute target row of each cross-range entry
@@ -328,13 +327,12 @@ struct TileBldArgs {
     const i64 *loc_ptr;
     const unsigned short *loc_tgt;
     const float *loc_w;
-    const i64 *loc_base;
     const double *rw;
     const unsigned *deg_flags;
     const double *inv_s;
-    const int *blk_ptr, *blk_ranges;
-    const TileRange *rinfo;  // per entry of blk_ranges: the range's first row, rows, local edges
-    i64 n, nranges;
+    const int *blk_ptr;
+    const TileRange *rinfo;  // the ranges grouped by workgroup (shares given by blk_ptr)
+    i64 n;
     int rb, k, K, rounds;
     int le_max;  // local edges of a range that fit the LDS edge buffer
     void *F;
@@ -1066,15 +1064,12 @@ static TileBldArgs tile_bld_args(BatchState *b, const DevGraph &g, const SweepPa
     a.loc_ptr = g.loc_ptr;
     a.loc_tgt = g.loc_tgt;
     a.loc_w = g.loc_w;
-    a.loc_base = g.loc_base;
     a.rw = g.rw;
     a.deg_flags = g.deg_flags;
     a.inv_s = g.inv_s;
     a.blk_ptr = b->blk_ptr;
-    a.blk_ranges = b->blk_ranges;
     a.rinfo = b->rinfo;
     a.n = b->n;
-    a.nranges = g.nranges;
     a.rb = g.rb;
     a.k = b->k;
     a.K = b->K;
@@ -1243,7 +1238,7 @@ void free_batch(BatchState *b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
     void *ps[] = {b->F,   b->F0,      b->H,         b->snap,  b->ctl,         b->partR,
-                  b->partC, b->partK, b->S,       b->fl,        b->blk_ptr, b->blk_ranges,
+                  b->partC, b->partK, b->S,       b->fl,        b->blk_ptr,
                   b->units, b->rem_tgt_abs, b->partH, b->hsum, b->rinfo, b->seg_row, b->seg_p0, b->seg_p1,
                   b->long_first, b->seg_part};
     for (void *q : ps)
@@ -1329,7 +1324,6 @@ static int assign_ranges(BatchState *b, const DevGraph &g) {
         ptr[q + 1] = (int)flat.size();
     }
     DI_HIP(hipMemcpy(b->blk_ptr, ptr.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice));
-    DI_HIP(hipMemcpy(b->blk_ranges, flat.data(), sizeof(int) * nr, hipMemcpyHostToDevice));
     std::vector<TileRange> info((size_t)nr);
     for (i64 q = 0; q < nr; ++q) {
         const i64 r = flat[q], base = r << g.rb;
@@ -1478,7 +1472,6 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
     if (b->bld) {
         if (!alloc(&b->S, n * k * T) || !alloc((void **)&b->fl, (size_t)((n + 31) / 32) * 4) ||
             !alloc((void **)&b->blk_ptr, (size_t)(b->gridB + 1) * 4) ||
-            !alloc((void **)&b->blk_ranges, (size_t)g.nranges * 4) ||
             !alloc((void **)&b->rinfo, (size_t)g.nranges * sizeof(TileRange)))
             return fail(DI_ENOMEM);
         int src = assign_ranges(b, g);
