@@ -631,7 +631,8 @@ def bench_update(g, theta, rounds, frac=0.01):
 def bench_adjoint():
     """Adjoint diffusion and edge gradients on the weighted webgen(2M, seed 5), double
     arithmetic: forward to a certified 1e-11, then di_adjoint for c ~ N(0, 1) to a certified
-    L-infinity 1e-11 (timed: the transposed diffusion and the per-edge gradient)."""
+    L-infinity 1e-11 (timed: the check of c, the transposed diffusion and the per-edge
+    gradient), with the library's default sweep options and with the autotuner's."""
     import numpy as np
     import workloads as W
     from paper_1501_06350_amd import binding as B
@@ -639,9 +640,17 @@ def bench_adjoint():
     g = W.webgen(2_000_000, 5, weighted=True)
     c = torch.from_numpy(W.normal_vector(g.n, 5)).cuda()  # resident in HBM; dZ and dw stay there too
     out = {"workload": "webgen n=%d m=%d seed=5, LogNormal(0,1) weights, c ~ N(0,1), f64, device arrays" % (g.n, g.m)}
+    from paper_1501_06350_amd import tune
     with B.from_graph(g, d=D) as s:
         s.diffuse(1e-11)
         s.adjoint(c, 1e-11)  # warm-up
+        (_, _, st0), ms0 = _timed(lambda: s.adjoint(c, 1e-11))
+        out["library_defaults"] = {"theta": 1.0, "inner_rounds": 4, "ms": round(ms0, 3), "sweeps": st0["sweeps"]}
+        # theta and the local rounds of the adjoint from the autotuner (outside the timed call)
+        t0 = time.time()
+        ta = tune.Tuner(None, log=log).tune_adjoint(s, c, tune.graph_key(g, 1, False, D, 1e-11), 1e-11)
+        out["adjoint_autotuner"] = dict(ta, seconds=round(time.time() - t0, 1))
+        s.adjoint(c, 1e-11)  # warm-up of the chosen setting
         (dZ, dw, st), ms = _timed(lambda: s.adjoint(c, 1e-11))
     out["adjoint_ms"] = round(ms, 3)
     out["sweeps"] = st["sweeps"]

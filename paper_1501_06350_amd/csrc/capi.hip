@@ -76,6 +76,8 @@ struct di_ctx {
     double *lam = nullptr;
     double *aF = nullptr;
     double *asnap = nullptr;
+    double *aZ = nullptr;   // dZ in the internal layout
+    u64 *achk = nullptr;    // check of g: max |g| (bits), first non-finite entry
     DevCtl *actl = nullptr;
     // fast adjoint: the transposed graph on the forward graph's ranges, and its two
     // in-flight buffers (values, then the bitmap of the nonzero ones)
@@ -133,6 +135,25 @@ int dalloc(di_ctx *c, T **p, i64 count) {
     if (count <= 0) count = 1;
     DI_HIP(hipMalloc((void **)p, (size_t)count * sizeof(T)));
     c->device_bytes += count * (i64)sizeof(T);
+    return DI_OK;
+}
+
+// launch order of a block-local graph's ranges: most work (edges inside plus entries
+// arriving from other ranges) first, so that the last workgroups of a sweep are short
+int make_range_order(di_ctx *c, const DevGraph &g, int **out) {
+    const i64 nr = g.nranges;
+    std::vector<i64> rbase(nr + 1), lbase(nr + 1);
+    if (hipMemcpy(rbase.data(), g.rem_base, sizeof(i64) * (nr + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(lbase.data(), g.loc_base, sizeof(i64) * (nr + 1), hipMemcpyDeviceToHost) != hipSuccess)
+        DI_FAIL(DI_EHIP, "range table download failed");
+    std::vector<int> order(nr);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (rbase[a + 1] - rbase[a]) + (lbase[a + 1] - lbase[a]) >
+               (rbase[b + 1] - rbase[b]) + (lbase[b + 1] - lbase[b]);
+    });
+    DI_TRY(dalloc(c, out, nr));
+    DI_HIP(hipMemcpy(*out, order.data(), sizeof(int) * nr, hipMemcpyHostToDevice));
     return DI_OK;
 }
 
@@ -616,6 +637,36 @@ __global__ void k_seg_to_internal(const double *__restrict__ src, double *dst, c
     }
 }
 
+// max |g_i| as the bits of a nonnegative double (they order like the values) into out[0],
+// and n - i for the first non-finite g_i into out[1] (0: none); out starts at zero
+__global__ void __launch_bounds__(256) k_check_rhs(const double *__restrict__ g, i64 n, u64 *out) {
+    __shared__ u64 red[2][256 / WAVE];
+    u64 mx = 0, bad = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const double v = g[i];
+        if (!__builtin_isfinite(v)) bad = max(bad, (u64)(n - i));
+        else mx = max(mx, (u64)__double_as_longlong(fabs(v)));
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        mx = max(mx, (u64)__shfl_xor((unsigned long long)mx, o, WAVE));
+        bad = max(bad, (u64)__shfl_xor((unsigned long long)bad, o, WAVE));
+    }
+    const int wv = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        red[0][wv] = mx;
+        red[1][wv] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // one atomic per block and value
+        for (int k = 1; k < 256 / WAVE; ++k) {
+            mx = max(mx, red[0][k]);
+            bad = max(bad, red[1][k]);
+        }
+        if (mx) atomicMax((unsigned long long *)&out[0], (unsigned long long)mx);
+        if (bad) atomicMax((unsigned long long *)&out[1], (unsigned long long)bad);
+    }
+}
+
 __global__ void k_seg_to_caller(const double *__restrict__ src, double *dst, const i64 *__restrict__ start, int rb,
                                 i64 n_int) {
     for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < n_int; q += (i64)gridDim.x * blockDim.x) {
@@ -715,7 +766,7 @@ int di_destroy(di_ctx *c) {
     free_row_blocks(c->rbout);
     void *ps[] = {c->s.F, c->s.F0, c->s.H, c->s.S[0], c->s.S[1], c->s.snap, c->s.frontier, c->s.range_order,
                   c->s.ctl, c->s.X[0], c->s.X[1], c->s.XT[0], c->s.XT[1], c->s.pctl, c->s.Z, c->lam,
-                  c->aF, c->asnap, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.range_cnt, c->d_seg_start, c->s.ginfo, c->s.gctl,
+                  c->aF, c->asnap, c->aZ, c->achk, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.range_cnt, c->d_seg_start, c->s.ginfo, c->s.gctl,
                   c->d_gp, c->d_gs, c->d_gscale, c->ref_ht, c->s.partH, c->s.hsum, c->aS[0], c->aS[1]};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -950,27 +1001,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     c->device_bytes += (2 * (n + 1) + 3 * n) * 8 + m * (4 + (w ? 4 : 0)) + c->g.m_loc * (2 + (w ? 4 : 0)) +
                        c->g.m_rem * (6 + (w ? 4 : 0)) + (c->g.nranges + 1) * 16;
 
-    // range order: most work first
-    {
-        const i64 nr = c->g.nranges;
-        std::vector<i64> rbase(nr + 1), lbase(nr + 1);
-        if (hipMemcpy(rbase.data(), c->g.rem_base, sizeof(i64) * (nr + 1), hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(lbase.data(), c->g.loc_base, sizeof(i64) * (nr + 1), hipMemcpyDeviceToHost) != hipSuccess) {
-            set_error("range table download failed");
-            return fail(DI_EHIP);
-        }
-        std::vector<int> order(nr);
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return (rbase[a + 1] - rbase[a]) + (lbase[a + 1] - lbase[a]) >
-                   (rbase[b + 1] - rbase[b]) + (lbase[b + 1] - lbase[b]);
-        });
-        if ((rc = dalloc(c, &c->s.range_order, nr))) return fail(rc);
-        if (hipMemcpy(c->s.range_order, order.data(), sizeof(int) * nr, hipMemcpyHostToDevice) != hipSuccess) {
-            set_error("range order upload failed");
-            return fail(DI_EHIP);
-        }
-    }
+    if ((rc = make_range_order(c, c->g, &c->s.range_order)) != DI_OK) return fail(rc);
 
     // cut-aligned ranges: the block-local sweeps skip the padding at the end of each range
     if (c->seg) {
@@ -1647,36 +1678,37 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         DI_TRY(dalloc(c, &c->lam, n));
         DI_TRY(dalloc(c, &c->aF, n));
         DI_TRY(dalloc(c, &c->asnap, n));
+        DI_TRY(dalloc(c, &c->aZ, n));
+        DI_TRY(dalloc(c, &c->achk, 2));
         DI_TRY(dalloc(c, &c->actl, 1));
     }
     const i64 nu = c->n_user;  // the caller's node count (n is internal)
-    std::vector<double> hg;
-    const double *gsrc = g;
+    // g checked on the device: a host g goes to the snapshot buffer (free until the sweeps
+    // start) first; nothing the caller can read changes before the check has passed
+    const double *gdev = g;
+    if (!on_device) {
+        DI_HIP(hipMemcpyAsync(c->asnap, g, sizeof(double) * nu, hipMemcpyHostToDevice, c->st));
+        gdev = c->asnap;
+    }
     double mx = 0.0;
     {
-        if (on_device) {
-            hg.resize((size_t)nu);
-            DI_HIP(hipMemcpy(hg.data(), g, sizeof(double) * nu, hipMemcpyDeviceToHost));
-            gsrc = hg.data();
-        }
-        for (i64 i = 0; i < nu; ++i) {
-            if (!std::isfinite(gsrc[i])) DI_FAIL(DI_EINVAL, "g[%lld] is not finite", (long long)i);
-            mx = std::max(mx, std::fabs(gsrc[i]));
-        }
+        DI_TRY(launch_fill_zero(c->achk, 16, c->st));
+        k_check_rhs<<<grid_for(nu, 256, 512), 256, 0, c->st>>>(gdev, nu, c->achk);
+        DI_LAUNCH_CHECK();
+        u64 hv[2] = {0, 0};
+        DI_HIP(hipMemcpyAsync(hv, c->achk, sizeof(hv), hipMemcpyDeviceToHost, c->st));
+        DI_HIP(hipStreamSynchronize(c->st));
+        if (hv[1]) DI_FAIL(DI_EINVAL, "g[%lld] is not finite", (long long)(nu - (i64)hv[1]));
+        std::memcpy(&mx, &hv[0], sizeof(mx));
     }
     SweepParams ap = c->p;
     ap.K = fixed_scale(mx, n);
     ap.tol = tol_inf;
     if (c->seg) {  // internal layout (padding nodes get no g), spread on the device
-        const double *gdev = g;
-        if (!on_device) {  // the snapshot buffer is free until the sweeps start
-            DI_HIP(hipMemcpyAsync(c->asnap, g, sizeof(double) * nu, hipMemcpyHostToDevice, c->st));
-            gdev = c->asnap;
-        }
         k_seg_to_internal<<<grid_for(n, 256, 16384), 256, 0, c->st>>>(gdev, c->aF, c->d_seg_start, c->seg_rb, n);
         DI_LAUNCH_CHECK();
     } else {
-        DI_HIP(hipMemcpyAsync(c->aF, gsrc, sizeof(double) * n, hipMemcpyHostToDevice, c->st));
+        DI_HIP(hipMemcpyAsync(c->aF, gdev, sizeof(double) * n, hipMemcpyDeviceToDevice, c->st));
     }
     DI_TRY(launch_fill_zero(c->lam, n * 8, c->st));
     DI_TRY(launch_fill_zero(c->actl, sizeof(DevCtl), c->st));
@@ -1766,17 +1798,15 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     double *ddZ = dZ, *ddw = dw;
     double *tZ = nullptr, *tw = nullptr;
     const bool zbuf = !on_device || c->seg, wbuf = !on_device && dw;
-    {
-        const bool ok = (!zbuf || hipMalloc((void **)&tZ, sizeof(double) * n) == hipSuccess) &&
-                        (!wbuf || hipMalloc((void **)&tw, sizeof(double) * std::max<i64>(c->g.m, 1)) == hipSuccess);
-        if (!ok) {
-            if (tZ) (void)hipFree(tZ);
+    if (zbuf) ddZ = tZ = c->aZ;
+    if (wbuf) {
+        if (hipMalloc((void **)&tw, sizeof(double) * std::max<i64>(c->g.m, 1)) != hipSuccess)
             DI_FAIL(DI_ENOMEM, "device allocation for the gradients failed");
-        }
-        if (zbuf) ddZ = tZ;
-        if (wbuf) ddw = tw;
+        ddw = tw;
     }
-    int rc = launch_edge_grad(c->g, c->s.H, c->lam, c->d, ddZ, ddw, c->st);
+    // fast contexts: the edge-parallel gradient with mu in the snapshot buffer (free once
+    // the sweeps are done); deterministic ones: the oracle's row-order sums
+    int rc = launch_edge_grad(c->g, c->s.H, c->lam, c->d, ddZ, ddw, c->o.deterministic ? nullptr : c->asnap, c->st);
     if (rc == DI_OK && c->seg) {  // dZ back to the caller's numbering (device dZ, or the snapshot buffer)
         double *zc = on_device ? dZ : c->asnap;
         k_seg_to_caller<<<grid_for(n, 256, 16384), 256, 0, c->st>>>(tZ, zc, c->d_seg_start, c->seg_rb, n);
@@ -1794,7 +1824,6 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         hipMemcpyAsync(dw, tw, sizeof(double) * c->g.m, hipMemcpyDeviceToHost, c->st) != hipSuccess)
         rc = DI_EHIP;
     if (hipStreamSynchronize(c->st) != hipSuccess) rc = DI_EHIP;
-    if (tZ) (void)hipFree(tZ);
     if (tw) (void)hipFree(tw);
     if (rc != DI_OK) DI_FAIL(rc, "adjoint gradient step failed");
     if (!on_device) std::memcpy(dZ, hz.data(), sizeof(double) * nu);

@@ -163,7 +163,9 @@ int launch_node_sums(const DevGraph &g, SolveState &s, const void *v, int is_flo
 int launch_adj_bld_sweep(const DevGraph &gT, const double *tinv, SolveState &as, const SweepParams &p, int rounds,
                          hipStream_t st);
 int launch_reduce_double(const double *F, i64 n, int K, DevCtl *ctl, hipStream_t st, u64 *partR, i64 *nR);
+// dZ = (1-d) lambda and, when dw is given, the edge gradient; with mu (n doubles of scratch)
+// the edge-parallel form, else the row-order sums of the oracle
 int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
-                     hipStream_t st);
+                     double *mu, hipStream_t st);
 
 }  // namespace di

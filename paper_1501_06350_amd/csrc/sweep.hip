@@ -1861,10 +1861,118 @@ __global__ void __launch_bounds__(256) k_edge_grad(const i64 *__restrict__ out_p
     for (i64 e = e0; e < e1; ++e) dw[e] = a * (lam[out_idx[e]] - mu);
 }
 
+// Edge-parallel form of the same gradient (fast contexts; the sums of mu run in another
+// order).  Each wave takes chunks of GE_CHUNK consecutive OUT edges; a chunk's rows come
+// in windows of 64 consecutive rows whose offsets sit in LDS, and a lane finds the row of
+// its edge there by binary search.  Pass 1 sums mu_j per window row in LDS: a row wholly
+// inside the chunk is stored, a row cut by a chunk boundary is added to mu atomically (mu
+// starts at zero).  Pass 2 writes dw_e = (d x_j inv_s_j)(lambda_target - mu_j) with the
+// window's per-row factors in LDS.  Every load and store of an edge is coalesced.
+constexpr int GE_CHUNK = 1024;
+constexpr int GE_WAVES = 4;
+
+template <bool WTD, bool DW>
+__global__ void __launch_bounds__(GE_WAVES * WAVE) k_edge_grad_fast(const i64 *__restrict__ out_ptr,
+                                                                   const int *__restrict__ out_idx,
+                                                                   const float *__restrict__ w,
+                                                                   const double *__restrict__ inv_s,
+                                                                   const double *__restrict__ x,
+                                                                   const double *__restrict__ lam, i64 n, i64 m,
+                                                                   double d, double *mu, double *dw) {
+    __shared__ i64 offs[GE_WAVES][WAVE + 1];
+    __shared__ double rowa[GE_WAVES][WAVE];  // pass 1: inv_s, pass 2: d x inv_s
+    __shared__ double rowb[GE_WAVES][WAVE];  // pass 1: sums of mu, pass 2: mu
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+    const i64 nch = (m + GE_CHUNK - 1) / GE_CHUNK;
+    for (i64 ch = (i64)blockIdx.x * GE_WAVES + wv; ch < nch; ch += (i64)gridDim.x * GE_WAVES) {
+        const i64 e0 = ch * GE_CHUNK, e1 = min(m, e0 + GE_CHUNK);
+        // the row holding edge e0, the last j with out_ptr[j] <= e0: 63 probes per step
+        // keep out_ptr[lo] <= e0 < out_ptr[hi]
+        i64 lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const i64 step = (hi - lo + WAVE - 1) / WAVE;
+            const i64 pr = lo + (i64)(lane + 1) * step;
+            const bool le = lane < WAVE - 1 && pr < hi && out_ptr[pr] <= e0;
+            const int c = __popcll(__ballot(le));  // the true probes form a prefix
+            lo += (i64)c * step;
+            hi = min(hi, lo + step);
+        }
+        i64 r0 = lo, es = e0;
+        while (es < e1) {
+            const i64 r = r0 + lane;
+            offs[wv][lane] = out_ptr[min(r, n)];
+            if (lane == 0) offs[wv][WAVE] = out_ptr[min(r0 + WAVE, n)];
+            if (r < n) {
+                const double inv = inv_s[r];
+                if (DW) {
+                    rowa[wv][lane] = d * x[r] * inv;
+                    rowb[wv][lane] = mu[r];
+                } else {
+                    rowa[wv][lane] = inv;
+                    rowb[wv][lane] = 0.0;
+                }
+            }
+            wave_sync_lds();
+            const i64 ee = min(e1, offs[wv][WAVE]);
+            for (i64 eb = es; eb < ee; eb += WAVE) {
+                // every lane runs each step (lanes past ee read edge ee-1 and add nothing)
+                const bool on = eb + lane < ee;
+                const i64 e = on ? eb + lane : ee - 1;
+                int l = 0;  // last l with offs[l] <= e
+#pragma unroll
+                for (int h = WAVE / 2; h > 0; h >>= 1)
+                    if (offs[wv][l + h] <= e) l += h;
+                const double lt = lam[out_idx[e]];
+                if (DW) {
+                    if (on) dw[e] = rowa[wv][l] * (lt - rowb[wv][l]);
+                } else {
+                    const double P = WTD ? (double)w[e] * rowa[wv][l] : rowa[wv][l];
+                    double v = on ? P * lt : 0.0;
+                    const int lf = __builtin_amdgcn_readfirstlane(l);
+                    if (__ballot(on && l != lf) == 0) {
+                        // one row under the whole step (long rows): a wave sum, one add
+                        for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+                        if (lane == 0) atomicAdd(&rowb[wv][lf], v);
+                    } else if (on) {
+                        atomicAdd(&rowb[wv][l], v);
+                    }
+                }
+            }
+            wave_sync_lds();
+            if (!DW && r < n) {
+                const i64 b = offs[wv][lane], f = offs[wv][lane + 1];
+                if (max(b, es) < min(f, ee)) {  // the row has edges in this chunk
+                    if (b >= e0 && f <= e1) mu[r] = rowb[wv][lane];
+                    else atomicAdd(&mu[r], rowb[wv][lane]);
+                }
+            }
+            wave_sync_lds();
+            r0 += WAVE;
+            es = ee;
+        }
+    }
+}
+
 int launch_edge_grad(const DevGraph &g, const double *x, const double *lam, double d, double *dZ, double *dw,
-                     hipStream_t st) {
-    if (g.weighted) k_edge_grad<true><<<grid_for(g.n, 256), 256, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, d, dZ, dw);
-    else k_edge_grad<false><<<grid_for(g.n, 256), 256, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, d, dZ, dw);
+                     double *mu, hipStream_t st) {
+    if (!mu || !dw) {  // row order (the oracle's sums), or dZ only
+        if (g.weighted) k_edge_grad<true><<<grid_for(g.n, 256), 256, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, d, dZ, dw);
+        else k_edge_grad<false><<<grid_for(g.n, 256), 256, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, d, dZ, dw);
+        DI_LAUNCH_CHECK();
+        return DI_OK;
+    }
+    DI_TRY(launch_scaled_copy(lam, 1.0 - d, g.n, dZ, st));
+    if (g.m == 0) return DI_OK;
+    DI_TRY(launch_fill_zero(mu, g.n * 8, st));
+    const i64 nch = (g.m + GE_CHUNK - 1) / GE_CHUNK;
+    const unsigned grid = (unsigned)std::min<i64>((nch + GE_WAVES - 1) / GE_WAVES, 8192);
+    if (g.weighted) {
+        k_edge_grad_fast<true, false><<<grid, GE_WAVES * WAVE, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, g.m, d, mu, dw);
+        k_edge_grad_fast<true, true><<<grid, GE_WAVES * WAVE, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, g.m, d, mu, dw);
+    } else {
+        k_edge_grad_fast<false, false><<<grid, GE_WAVES * WAVE, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, g.m, d, mu, dw);
+        k_edge_grad_fast<false, true><<<grid, GE_WAVES * WAVE, 0, st>>>(g.out_ptr, g.out_idx, g.w, g.inv_s, x, lam, g.n, g.m, d, mu, dw);
+    }
     DI_LAUNCH_CHECK();
     return DI_OK;
 }

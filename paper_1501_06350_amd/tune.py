@@ -3,7 +3,8 @@
 The block-local sweep has three knobs whose best values depend on the graph: the frontier
 scale theta (a node is taken when |F_i| >= theta |F|_1 / n), the local rounds per sweep,
 and the range size 2^range_log2 (the k-column tile's range size is fixed by the LDS its
-k columns need, so only theta and the rounds are tuned there).  The tuner times complete
+k columns need, so only theta and the rounds are tuned there; the adjoint diffusion runs on
+the forward context's ranges, so it too tunes theta and the rounds only).  The tuner times complete
 solves to the caller's tolerance on the caller's graph through the library (all arithmetic
 runs in the HIP kernels; this module only chooses options and keeps a cache):
 
@@ -32,6 +33,8 @@ ROUNDS = (4, 6, 8)
 RANGE_LOG2 = (10, 11)
 TILE_THETAS = (0.3, 0.5, 1.0)
 TILE_ROUNDS = (2, 4, 6)
+ADJ_THETAS = (0.5, 1.0)
+ADJ_ROUNDS = (4, 6, 8)
 
 
 def default_cache_path() -> str:
@@ -184,3 +187,40 @@ class Tuner:
         self.cache[key] = res
         self._save()
         return dict(res, cached=False)
+
+    def tune_adjoint(self, s, rhs, key: str, tol_inf: float = 1e-11, thetas=ADJ_THETAS, rounds=ADJ_ROUNDS,
+                     force: bool = False) -> dict:
+        """theta and rounds for the adjoint diffusion of a live context s whose forward solve
+        has converged: complete di_adjoint calls for the right-hand side rhs, timed by their
+        device clock.  The context is left with the chosen options (they also apply to its
+        later forward sweeps).  key names the workload in the cache (see graph_key)."""
+        key = "adjoint " + key
+        if not force and key in self.cache:
+            res = dict(self.cache[key], cached=True)
+        else:
+            def run():
+                _, _, st = s.adjoint(rhs, tol_inf, want_dw=False)
+                return float(st["ms"]) if st["converged"] else float("inf")
+
+            first = []
+            for th in thetas:
+                for rd in rounds:
+                    s.set_options(theta=th, inner_rounds=rd)
+                    run()  # warm-up of this setting
+                    ms = run()
+                    first.append((ms, th, rd))
+                    self.log("tune adjoint: theta=%g rounds=%d: %.2f ms" % (th, rd, ms))
+            first.sort()
+            best = None
+            for _, th, rd in first[: self.finalists]:
+                s.set_options(theta=th, inner_rounds=rd)
+                med = statistics.median([run() for _ in range(self.repeats)])
+                self.log("tune adjoint: finalist theta=%g rounds=%d: median %.2f ms" % (th, rd, med))
+                if best is None or med < best[0]:
+                    best = (med, th, rd)
+            res = {"theta": best[1], "inner_rounds": best[2], "ms": round(best[0], 3)}
+            self.cache[key] = res
+            self._save()
+            res = dict(res, cached=False)
+        s.set_options(theta=res["theta"], inner_rounds=res["inner_rounds"])
+        return res

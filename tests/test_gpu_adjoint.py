@@ -97,6 +97,25 @@ def test_fast_adjoint_against_oracle(gpu, name, fp32):
             assert err <= st["bound"] + 2e-14
             assert err <= 1e-9 * np.abs(lo).max()
             np.testing.assert_allclose(dZ, (1 - D) * lam, rtol=1e-15, atol=0)
+            check_fast_dw(og, g, s.read(gpu.H), lam, dw)
+
+
+def check_fast_dw(og, g, x, lam, dw):
+    """The edge-parallel gradient of fast contexts against the oracle's formula evaluated on
+    the same x and lambda: only the order of the sums of mu differs, so every edge agrees to
+    a few ulps of d x_j / s_j |lambda|_inf times the row length."""
+    dw_o, _ = O.edge_grad(og, D, x, lam)
+    deg = np.diff(np.asarray(g.out_ptr, dtype=np.int64))
+    if getattr(g, "w", None) is not None:
+        s_j = np.add.reduceat(np.asarray(g.w, dtype=np.float64), np.asarray(g.out_ptr[:-1], dtype=np.int64)) \
+            if g.m else np.zeros(g.n)
+        s_j = np.where(deg > 0, s_j, 1.0)
+    else:
+        s_j = np.maximum(deg, 1).astype(np.float64)
+    a = np.repeat(D * np.abs(x) / s_j, deg)
+    tol = a * (np.repeat(deg, deg) + 2) * 4e-16 * np.abs(lam).max()
+    err = np.abs(dw - dw_o)
+    assert np.all(err <= tol + 1e-300), "worst edge %d: %.3e > %.3e" % (err.argmax(), err.max(), tol[err.argmax()])
 
 
 def test_duality_and_sampled_rows_at_scale(gpu):
@@ -127,6 +146,31 @@ def test_duality_and_sampled_rows_at_scale(gpu):
         assert abs(r) <= sta["bound"] * (1 - D) * 1.0001 + 1e-12
     # dZ is (1-d) lambda
     np.testing.assert_allclose(dZ, (1 - D) * lam, rtol=1e-15, atol=0)
+    # every edge of the gradient against the oracle's formula on the same x and lambda
+    check_fast_dw(O.OGraph.of(g), g, x, lam, dw)
+
+
+@pytest.mark.parametrize("on_device", [False, True])
+def test_adjoint_rejects_non_finite_g(gpu, on_device):
+    """g is checked on the device; a non-finite entry is refused by its index and the last
+    lambda stays readable and unchanged."""
+    import torch
+    g = W.webgen(20_000, 14, weighted=True)
+    c = W.normal_vector(g.n, 3)
+    with gpu.from_graph(g, d=D) as s:
+        s.diffuse(1e-11)
+        s.adjoint(c, 1e-11)
+        lam = s.read(gpu.LAMBDA)
+        for bad, i in ((np.nan, 12345), (np.inf, 0), (-np.inf, g.n - 1)):
+            cb = c.copy()
+            cb[i] = bad
+            arg = torch.from_numpy(cb).cuda() if on_device else cb
+            with pytest.raises(gpu.DIError) as e:
+                s.adjoint(arg, 1e-11)
+            assert e.value.code == gpu.DI_EINVAL and ("g[%d]" % i) in str(e.value)
+            assert np.array_equal(s.read(gpu.LAMBDA), lam)
+        dZ, dw, st = s.adjoint(c, 1e-11)
+        assert st["converged"] and np.abs(s.read(gpu.LAMBDA) - lam).max() <= 2e-11
 
 
 @pytest.fixture(scope="module")

@@ -63,3 +63,24 @@ def test_set_sweep_on_a_live_context(gpu):
             s.set_options(-1.0, 4)
         with pytest.raises(gpu.DIError):
             s.set_options(1.0, 65)
+
+
+@pytest.mark.gpu
+def test_tuner_adjoint(gpu, tmp_path):
+    g = W.webgen(30_000, 9, weighted=True)
+    c = W.normal_vector(g.n, 4)
+    path = str(tmp_path / "tune.json")
+    key = tune.graph_key(g, 1, False, D, 1e-11)
+    og = O.OGraph.of(g)
+    lam_o, _, _, conv = O.adjoint(og, D, c, tol_inf=1e-14)
+    assert conv
+    with gpu.from_graph(g, d=D) as s:
+        s.diffuse(1e-11)
+        r = tune.Tuner(path, repeats=2, finalists=2).tune_adjoint(s, c, key, 1e-11, thetas=(0.5, 1.0), rounds=(4, 6))
+        assert not r["cached"] and r["theta"] in (0.5, 1.0) and r["inner_rounds"] in (4, 6) and r["ms"] > 0
+        assert s.info(gpu.INFO_INNER_ROUNDS) == r["inner_rounds"]
+        r2 = tune.Tuner(path).tune_adjoint(s, c, key, 1e-11)
+        assert r2["cached"] and r2["theta"] == r["theta"] and r2["inner_rounds"] == r["inner_rounds"]
+        # the chosen options reach the tolerance
+        _, _, st = s.adjoint(c, 1e-11)
+        assert st["converged"] and np.abs(s.read(gpu.LAMBDA) - lam_o).max() <= st["bound"] + 2e-14
