@@ -18,6 +18,18 @@
  *
  * Thread safety: one context is used by one host thread at a time; independent
  * contexts are independent.  All device work of a context runs on its stream.
+ *
+ * Environment (read at each use):
+ *   DI_LOG=path          append JSON lines to path: one per host synchronisation of
+ *                        di_diffuse, di_power and di_adjoint (every sweeps_per_sync sweeps;
+ *                        1 gives one per sweep: sweep index, the call's sweeps, node and
+ *                        edge updates and DI rounds so far, residual, bounds, leak, host
+ *                        ms) and one at the end of each such call (plus status,
+ *                        converged, mass defect, device ms, GEUPS).  Best effort: a file
+ *                        that cannot be opened is skipped, never an error.
+ *   DI_FAIL_ALLOC_AT=k   for tests of the error paths: the k-th device allocation after
+ *                        the variable took its current value fails as out of memory
+ *                        (the call returns DI_ENOMEM and frees what it had allocated).
  */
 #ifndef DI_API_H_
 #define DI_API_H_
@@ -299,6 +311,8 @@ int di_load(di_ctx *ctx, const char *path);
 #define DI_INFO_M_REMOTE 13       /* cross-range edges */
 #define DI_INFO_NRANGES 14        /* block-local ranges */
 #define DI_INFO_N_INTERNAL 15     /* nodes held on the device (n plus the padding of a union) */
+#define DI_INFO_LIVE_ALLOCATIONS 16 /* device allocations the library holds in this process, all
+                                       contexts together (ctx may be NULL for this key) */
 int di_info(di_ctx *ctx, int key, int64_t *value);
 
 /* Release everything; NULL-safe. */

@@ -23,7 +23,7 @@ X_RAW, X_NORM, F, H, LAMBDA, X_PI, IN_PTR, IN_IDX, INV_S, FRONTIER, RESIDUALS, L
     MASS_DEFECTS = range(14)
 INFO_N, INFO_M, INFO_K, INFO_M_LOCAL, INFO_RANGE_LOG2, INFO_INNER_ROUNDS, INFO_FIXED_K, INFO_TOTAL_SWEEPS, \
     INFO_DEVICE_BYTES, INFO_KERNEL_NS, INFO_KERNEL_LAUNCHES, INFO_LOCAL_PUSHES, INFO_REMOTE_UPDATES, INFO_M_REMOTE, \
-    INFO_NRANGES, INFO_N_INTERNAL = range(16)
+    INFO_NRANGES, INFO_N_INTERNAL, INFO_LIVE_ALLOCATIONS = range(17)
 
 EXPORTED = ["di_init", "di_diffuse", "di_power", "di_power_noalloc", "di_adjoint", "di_read", "di_update",
             "di_set_sweep", "di_reset", "di_set_z", "di_save", "di_load", "di_info", "di_destroy", "di_last_error"]
@@ -313,6 +313,13 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+def live_allocations() -> int:
+    """Device allocations the library holds in this process (all contexts)."""
+    v = ctypes.c_int64(0)
+    _check(load_library().di_info(None, INFO_LIVE_ALLOCATIONS, ctypes.byref(v)))
+    return int(v.value)
 
 
 def from_graph(g, **kw) -> Solver:

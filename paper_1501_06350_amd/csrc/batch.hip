@@ -1242,7 +1242,7 @@ void free_batch(BatchState *b) {
                   b->units, b->rem_tgt_abs, b->partH, b->hsum, b->rinfo, b->seg_row, b->seg_p0, b->seg_p1,
                   b->long_first, b->seg_part};
     for (void *q : ps)
-        if (q) (void)hipFree(q);
+        if (q) (void)dev_free(q);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
@@ -1370,8 +1370,8 @@ static int build_delivery_units(BatchState *b, const DevGraph &g) {
     if (cur.len) units.push_back(cur);
     b->nunits = (i64)units.size();
     b->gridD = (int)std::min<i64>(DL_GRID, (b->nunits + DL_WAVES - 1) / DL_WAVES);
-    if (hipMalloc((void **)&b->units, sizeof(DlUnit) * units.size()) != hipSuccess ||
-        hipMalloc((void **)&b->rem_tgt_abs, sizeof(int) * mr) != hipSuccess) {
+    if (dev_malloc((void **)&b->units, sizeof(DlUnit) * units.size()) != hipSuccess ||
+        dev_malloc((void **)&b->rem_tgt_abs, sizeof(int) * mr) != hipSuccess) {
         set_error("device allocation of the delivery units failed");
         return DI_ENOMEM;
     }
@@ -1400,11 +1400,11 @@ static int build_refine_segments(BatchState *b, const DevGraph &g) {
     b->nlong = (i64)lfirst.size();
     lfirst.push_back((int)srow.size());
     if (b->nseg == 0) return DI_OK;
-    if (hipMalloc((void **)&b->seg_row, sizeof(int) * srow.size()) != hipSuccess ||
-        hipMalloc((void **)&b->seg_p0, 8 * sp0.size()) != hipSuccess ||
-        hipMalloc((void **)&b->seg_p1, 8 * sp1.size()) != hipSuccess ||
-        hipMalloc((void **)&b->long_first, 4 * lfirst.size()) != hipSuccess ||
-        hipMalloc((void **)&b->seg_part, 8 * (size_t)KMAX * srow.size()) != hipSuccess) {
+    if (dev_malloc((void **)&b->seg_row, sizeof(int) * srow.size()) != hipSuccess ||
+        dev_malloc((void **)&b->seg_p0, 8 * sp0.size()) != hipSuccess ||
+        dev_malloc((void **)&b->seg_p1, 8 * sp1.size()) != hipSuccess ||
+        dev_malloc((void **)&b->long_first, 4 * lfirst.size()) != hipSuccess ||
+        dev_malloc((void **)&b->seg_part, 8 * (size_t)KMAX * srow.size()) != hipSuccess) {
         set_error("device allocation of the recomputation segments failed");
         return DI_ENOMEM;
     }
@@ -1455,7 +1455,7 @@ int init_batch(BatchState *&bout, const DevGraph &g, SweepParams &p, int k, int 
         return code;
     };
     auto alloc = [&](void **ptr, size_t bytes) -> bool {
-        if (hipMalloc(ptr, bytes) == hipSuccess) return true;
+        if (dev_malloc(ptr, bytes) == hipSuccess) return true;
         set_error("device allocation of %zu bytes failed", bytes);
         return false;
     };
@@ -1720,15 +1720,15 @@ int read_batch(BatchState *b, const DevGraph &g, const SweepParams &p, int what,
             const double l = limbs_to_double_signed(h.limbsL[c][0], h.limbsL[c][1], h.limbsL[c][2], h.limbsL[c][3], b->K);
             sc[c] = (1.0 - p.d) / (1.0 - p.d - p.d * l / b->zsum[c]);
         }
-        DI_HIP(hipMalloc((void **)&scale, sizeof(double) * k));
+        DI_HIP(dev_malloc((void **)&scale, sizeof(double) * k));
         if (hipMemcpy(scale, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(scale);
+            (void)dev_free(scale);
             set_error("upload of the completion scales failed");
             return DI_EHIP;
         }
     }
     hipError_t e = hipSuccess;
-    if (!on_device) e = hipMalloc((void **)&out, sizeof(double) * std::max<i64>(n * k, 1));
+    if (!on_device) e = dev_malloc((void **)&out, sizeof(double) * std::max<i64>(n * k, 1));
     if (e == hipSuccess) {
         const unsigned grid = grid_for(n * k, 256, 16384);
         if (what == DI_F && b->fp32) k_tile_to_colmajor<float><<<grid, 256, 0, st>>>((const float *)b->F, n, k, nullptr, out);
@@ -1737,9 +1737,9 @@ int read_batch(BatchState *b, const DevGraph &g, const SweepParams &p, int what,
         e = hipGetLastError();
         if (e == hipSuccess && !on_device) e = hipMemcpyAsync(dst, out, sizeof(double) * n * k, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (!on_device) (void)hipFree(out);
+        if (!on_device) (void)dev_free(out);
     }
-    if (scale) (void)hipFree(scale);
+    if (scale) (void)dev_free(scale);
     if (e != hipSuccess) {
         set_error("batched read failed: %s", hipGetErrorString(e));
         return DI_EHIP;

@@ -1,5 +1,6 @@
 // C ABI of the library: validation, context management and the host-side sweep loop.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -7,6 +8,7 @@
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <string>
 
 #include "batch.h"
 #include "sweep.h"
@@ -28,11 +30,58 @@ void set_error(const char *fmt, ...) {
         return (code);                \
     } while (0)
 
+// ---------------------------------------------------------------------------
+// Device allocations: live count and injected failures (DI_FAIL_ALLOC_AT)
+// ---------------------------------------------------------------------------
+std::mutex g_alloc_mu;
+long long g_alloc_live = 0;
+long long g_alloc_seen = 0;  // allocations since DI_FAIL_ALLOC_AT took its current value
+std::string g_alloc_env;
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        const char *e = std::getenv("DI_FAIL_ALLOC_AT");
+        const std::string v = e ? e : "";
+        if (v != g_alloc_env) {
+            g_alloc_env = v;
+            g_alloc_seen = 0;
+        }
+        const long long k = v.empty() ? 0 : std::atoll(v.c_str());
+        if (k > 0 && ++g_alloc_seen == k) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    const hipError_t r = hipMalloc(p, bytes);
+    if (r == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        ++g_alloc_live;
+    }
+    return r;
+}
+
+hipError_t dev_free(void *p) {
+    if (!p) return hipSuccess;
+    const hipError_t r = hipFree(p);
+    if (r == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        --g_alloc_live;
+    }
+    return r;
+}
+
+long long dev_live_allocations() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc_live;
+}
+
 }  // namespace di
 
 using namespace di;
 
 struct di_ctx {
+    std::chrono::steady_clock::time_point call_t0;  // start of the running API call (DI_LOG)
     DevGraph g;
     RowBlocks rbin;  // row blocks of IN (power iteration, fluid recomputation)
     bool rbin_ready = false;
@@ -133,7 +182,7 @@ template <typename T>
 int dalloc(di_ctx *c, T **p, i64 count) {
     *p = nullptr;
     if (count <= 0) count = 1;
-    DI_HIP(hipMalloc((void **)p, (size_t)count * sizeof(T)));
+    DI_HIP(dev_malloc((void **)p, (size_t)count * sizeof(T)));
     c->device_bytes += count * (i64)sizeof(T);
     return DI_OK;
 }
@@ -227,10 +276,21 @@ __global__ void k_ctl_begin(DevCtl *c, long long max_sweeps) {
 
 int ensure_row_blocks(di_ctx *c) {
     if (!c->rbin_ready) {
-        DI_TRY(build_row_blocks(c->rbin, c->g.in_ptr, c->g.n, c->st));
+        const int rc = build_row_blocks(c->rbin, c->g.in_ptr, c->g.n, c->st);
+        if (rc != DI_OK) {  // nothing half-built stays behind
+            free_row_blocks(c->rbin);
+            return rc;
+        }
         c->rbin_ready = true;
     }
     return DI_OK;
+}
+
+// Frees the device buffers of a lazily allocated group and nulls them, after one of its
+// allocations failed: the next call allocates the whole group again.
+template <typename... P>
+void free_group(P **...ps) {
+    ((*ps ? (void)dev_free((void *)*ps) : (void)0, *ps = nullptr), ...);
 }
 
 __global__ void k_ctl_reopen(DevCtl *c) { c->done = 0; }
@@ -376,6 +436,64 @@ void fill_stats(di_stats *st, const DevCtl &h, const DevCtl &before, double d, i
     st->ms = ms;
     st->mass_defect = 0.0;
     st->converged = h.done && !h.overflow;
+}
+
+// ---------------------------------------------------------------------------
+// DI_LOG: when the environment names a file, every host synchronisation of a solve loop
+// (every sweeps_per_sync sweeps; 1 gives a record per sweep) and the end of every
+// di_diffuse, di_power and di_adjoint call append one JSON line to it: the call, the
+// context, the sweep index, the call's counters so far, DI rounds (diffusions / n), the
+// residual, the certified bounds, the leak and the host time since the call began.  The
+// end record adds the status, the convergence flag, the mass defect, the device time and
+// the GEUPS.  The variable is read at every record; unset or empty, nothing is written.
+// ---------------------------------------------------------------------------
+std::mutex g_log_mu;
+FILE *g_log_file = nullptr;
+std::string g_log_path;
+
+bool log_on() {
+    const char *p = std::getenv("DI_LOG");
+    return p && *p;
+}
+
+void log_line(const char *line) {
+    const char *p = std::getenv("DI_LOG");
+    if (!p || !*p) return;
+    std::lock_guard<std::mutex> lk(g_log_mu);
+    if (!g_log_file || g_log_path != p) {
+        if (g_log_file) fclose(g_log_file);
+        g_log_file = fopen(p, "a");
+        g_log_path = p;
+        if (!g_log_file) return;  // logging is best effort: a solve never fails for it
+    }
+    fputs(line, g_log_file);
+    fputc('\n', g_log_file);
+    fflush(g_log_file);
+}
+
+void log_record(const di_ctx *c, i64 n, const char *call, const char *event, long long sweep, const di_stats &s,
+                const int *status) {
+    if (!log_on()) return;
+    const double host_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c->call_t0).count();
+    char buf[1024];
+    int k = snprintf(buf, sizeof(buf),
+                     "{\"call\":\"%s\",\"event\":\"%s\",\"ctx\":\"%p\",\"sweep\":%lld,\"sweeps\":%lld,"
+                     "\"node_updates\":%lld,\"edge_updates\":%lld,\"rounds\":%.6g,\"residual\":%.17g,"
+                     "\"bound\":%.17g,\"bound_norm\":%.17g,\"leak\":%.17g,\"host_ms\":%.3f",
+                     call, event, (const void *)c, sweep, (long long)s.sweeps, (long long)s.node_updates,
+                     (long long)s.edge_updates, n > 0 ? (double)s.node_updates / (double)n : 0.0, s.residual, s.bound,
+                     s.bound_norm, s.leak, host_ms);
+    if (status && k > 0 && k < (int)sizeof(buf))
+        k += snprintf(buf + k, sizeof(buf) - k,
+                      ",\"status\":%d,\"converged\":%d,\"mass_defect\":%.17g,\"device_ms\":%.4f,\"geups\":%.6g",
+                      *status, s.converged, s.mass_defect, s.ms,
+                      s.ms > 0 ? (double)s.edge_updates / (s.ms * 1e6) : 0.0);
+    if (k > 0 && k < (int)sizeof(buf) - 2) {
+        buf[k] = '}';
+        buf[k + 1] = 0;
+        log_line(buf);
+    }
 }
 
 // Internal (padded) layout of a union of graphs -> caller's numbering, times a per-graph
@@ -529,23 +647,26 @@ int upload_segmented(di_ctx *c, const i64 *ptr, const int *idx, const float *w, 
     i64 *excl = nullptr, *temp = nullptr;
     auto cleanup = [&]() {
         for (void *q : {(void *)d_ptr, (void *)diff, (void *)excl, (void *)temp})
-            if (q) (void)hipFree(q);
+            if (q) (void)dev_free(q);
     };
+    hipError_t last = hipSuccess;
     auto hip_ok = [&](hipError_t e) {
         if (e == hipSuccess) return true;
+        last = e;
         set_error("cut-aligned range layout: %s", hipGetErrorString(e));
         return false;
     };
-    if (!hip_ok(hipMalloc((void **)&d_ptr, sizeof(i64) * (n + 1))) ||
-        !hip_ok(hipMalloc((void **)&d_idx, sizeof(int) * std::max<i64>(m, 1))) ||
-        !hip_ok(hipMalloc((void **)&diff, sizeof(i64) * (n + 2))) ||
-        !hip_ok(hipMalloc((void **)&excl, sizeof(i64) * (n + 2))) ||
-        !hip_ok(hipMalloc((void **)&temp, sizeof(i64) * (scan_temp_elems(n + 2) + 64))) ||
+    auto hip_code = [&]() { return last == hipErrorOutOfMemory ? DI_ENOMEM : DI_EHIP; };
+    if (!hip_ok(dev_malloc((void **)&d_ptr, sizeof(i64) * (n + 1))) ||
+        !hip_ok(dev_malloc((void **)&d_idx, sizeof(int) * std::max<i64>(m, 1))) ||
+        !hip_ok(dev_malloc((void **)&diff, sizeof(i64) * (n + 2))) ||
+        !hip_ok(dev_malloc((void **)&excl, sizeof(i64) * (n + 2))) ||
+        !hip_ok(dev_malloc((void **)&temp, sizeof(i64) * (scan_temp_elems(n + 2) + 64))) ||
         !hip_ok(hipMemcpy(d_ptr, ptr, sizeof(i64) * (n + 1), hipMemcpyHostToDevice)) ||
         (m && !hip_ok(hipMemcpy(d_idx, idx, sizeof(int) * m, hipMemcpyHostToDevice)))) {
         cleanup();
-        if (d_idx) (void)hipFree(d_idx);
-        return DI_EHIP;
+        if (d_idx) (void)dev_free(d_idx);
+        return hip_code();
     }
     c->g.out_idx = d_idx;  // owned by the context from here on
     int rc = launch_fill_zero(diff, sizeof(i64) * (n + 2), c->st);
@@ -594,15 +715,15 @@ int upload_segmented(di_ctx *c, const i64 *ptr, const int *idx, const float *w, 
     i64 *d_start = nullptr;
     int *d_coarse = nullptr;
     i64 *pptr = nullptr;
-    if (!hip_ok(hipMalloc((void **)&d_start, sizeof(i64) * (nr + 1))) ||
-        !hip_ok(hipMalloc((void **)&d_coarse, sizeof(int) * coarse.size())) ||
-        !hip_ok(hipMalloc((void **)&pptr, sizeof(i64) * (n_int + 1))) ||
+    if (!hip_ok(dev_malloc((void **)&d_start, sizeof(i64) * (nr + 1))) ||
+        !hip_ok(dev_malloc((void **)&d_coarse, sizeof(int) * coarse.size())) ||
+        !hip_ok(dev_malloc((void **)&pptr, sizeof(i64) * (n_int + 1))) ||
         !hip_ok(hipMemcpy(d_start, start.data(), sizeof(i64) * (nr + 1), hipMemcpyHostToDevice)) ||
         !hip_ok(hipMemcpy(d_coarse, coarse.data(), sizeof(int) * coarse.size(), hipMemcpyHostToDevice))) {
         for (void *q : {(void *)d_start, (void *)d_coarse, (void *)pptr})
-            if (q) (void)hipFree(q);
+            if (q) (void)dev_free(q);
         cleanup();
-        return DI_EHIP;
+        return hip_code();
     }
     k_pad_rows<<<grid_for(n_int + 1, 256, 16384), 256, 0, c->st>>>(d_ptr, d_start, nr, rb, n_int, m, pptr);
     hipError_t e = hipGetLastError();
@@ -611,12 +732,12 @@ int upload_segmented(di_ctx *c, const i64 *ptr, const int *idx, const float *w, 
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-    (void)hipFree(d_coarse);
+    (void)dev_free(d_coarse);
     cleanup();
     if (!hip_ok(e)) {
-        (void)hipFree(pptr);
-        (void)hipFree(d_start);
-        return DI_EHIP;
+        (void)dev_free(pptr);
+        (void)dev_free(d_start);
+        return hip_code();
     }
     c->d_seg_start = d_start;
     c->g.out_ptr = pptr;
@@ -769,7 +890,7 @@ int di_destroy(di_ctx *c) {
                   c->aF, c->asnap, c->aZ, c->achk, c->actl, c->s.partR, c->s.partC, c->s.range_graph, c->s.range_cnt, c->d_seg_start, c->s.ginfo, c->s.gctl,
                   c->d_gp, c->d_gs, c->d_gscale, c->ref_ht, c->s.partH, c->s.hsum, c->aS[0], c->aS[1]};
     for (void *p : ps)
-        if (p) (void)hipFree(p);
+        if (p) (void)dev_free(p);
     if (c->b) free_batch(c->b);
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
@@ -1180,7 +1301,7 @@ int di_set_z(di_ctx *c, const double *Z) {
             if (!c->s.Z) DI_TRY(dalloc(c, &c->s.Z, n));
             DI_HIP(hipMemcpy(c->s.Z, c->seg ? zint.data() : Z, sizeof(double) * n, hipMemcpyHostToDevice));
         } else if (c->s.Z) {
-            (void)hipFree(c->s.Z);
+            (void)dev_free(c->s.Z);
             c->s.Z = nullptr;
         }
         c->s.zc = (1.0 - c->d) * (1.0 / (double)n);  // read when s.Z is null (uniform Z)
@@ -1201,7 +1322,55 @@ int di_set_z(di_ctx *c, const double *Z) {
     return reset_state(c);
 }
 
+static int diffuse_call(di_ctx *c, double tol, di_stats *st);
+static int power_call(di_ctx *c, double tol, di_stats *st);
+static int adjoint_call(di_ctx *c, const double *g, double tol_inf, double *dZ, double *dw, int on_device,
+                        di_stats *st);
+
+// the end record of DI_LOG for a finished call (stats from the call, or zeros)
+static void log_end(di_ctx *c, const char *call, const di_stats &s, int rc) {
+    if (c && log_on()) log_record(c, c->n_user, call, "end", c->h_ctl ? c->h_ctl->sweep : -1, s, &rc);
+}
+
+static void log_adjoint_sync(di_ctx *c, const DevCtl &h, const DevCtl &before) {
+    if (!log_on()) return;
+    di_stats ls{};
+    ls.sweeps = h.sweep - before.sweep;
+    ls.edge_updates = (int64_t)(h.tot_edges - before.tot_edges);
+    ls.node_updates = (int64_t)(h.tot_nodes - before.tot_nodes);
+    ls.residual = h.R;
+    ls.bound = ls.bound_norm = h.maxF / (1.0 - c->d);
+    log_record(c, c->n_user, "adjoint", "sync", h.sweep, ls, nullptr);
+}
+
 int di_diffuse(di_ctx *c, double tol, di_stats *st) {
+    if (c) c->call_t0 = std::chrono::steady_clock::now();
+    di_stats loc{};
+    di_stats *sp = st ? st : &loc;
+    const int rc = diffuse_call(c, tol, sp);
+    log_end(c, "diffuse", *sp, rc);
+    return rc;
+}
+
+int di_power(di_ctx *c, double tol, di_stats *st) {
+    if (c) c->call_t0 = std::chrono::steady_clock::now();
+    di_stats loc{};
+    di_stats *sp = st ? st : &loc;
+    const int rc = power_call(c, tol, sp);
+    log_end(c, "power", *sp, rc);
+    return rc;
+}
+
+int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *dw, int on_device, di_stats *st) {
+    if (c) c->call_t0 = std::chrono::steady_clock::now();
+    di_stats loc{};
+    di_stats *sp = st ? st : &loc;
+    const int rc = adjoint_call(c, g, tol_inf, dZ, dw, on_device, sp);
+    log_end(c, "adjoint", *sp, rc);
+    return rc;
+}
+
+static int diffuse_call(di_ctx *c, double tol, di_stats *st) {
     if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
     if (!(tol > 0.0) || !std::isfinite(tol)) DI_FAIL(DI_EINVAL, "tol must be finite and > 0");
     c->p.tol = tol;
@@ -1278,6 +1447,11 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
         DI_TRY(sync_ctl(c, c->s.ctl));
         in_flight = true;
         const DevCtl &h = *c->h_ctl;
+        if (log_on()) {
+            di_stats ls{};
+            fill_stats(&ls, h, before, c->d, c->p.K, 0.0f, false, c->zsum);
+            log_record(c, c->n_user, "diffuse", "sync", h.sweep, ls, nullptr);
+        }
         if (c->o.timing && c->o.loop_mode == DI_LOOP_STREAM) DI_TRY(collect_timing(c, h.sweep - s0));
         if (h.overflow) break;
         if (refine && (h.done || h.R <= R_ref * REFINE_DROP)) {
@@ -1314,19 +1488,23 @@ int di_diffuse(di_ctx *c, double tol, di_stats *st) {
     return DI_OK;
 }
 
-int di_power(di_ctx *c, double tol, di_stats *st) {
+static int power_call(di_ctx *c, double tol, di_stats *st) {
     if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
     if (!(tol > 0.0) || !std::isfinite(tol)) DI_FAIL(DI_EINVAL, "tol must be finite and > 0");
     if (c->k != 1 || c->n_graphs != 1) DI_FAIL(DI_EINVAL, "di_power supports one right-hand side on one graph");
     const i64 n = c->g.n;
     const size_t T = c->p.fp32 ? 4 : 8;
     if (!c->pi_ready) {
-        DI_TRY(ensure_row_blocks(c));
-        DI_TRY(dalloc(c, &c->s.X[0], n));
-        DI_TRY(dalloc(c, &c->s.X[1], n));
-        DI_TRY(dalloc(c, (char **)&c->s.XT[0], n * T));
-        DI_TRY(dalloc(c, (char **)&c->s.XT[1], n * T));
-        DI_TRY(dalloc(c, &c->s.pctl, 1));
+        int rc = ensure_row_blocks(c);
+        if (rc == DI_OK) rc = dalloc(c, &c->s.X[0], n);
+        if (rc == DI_OK) rc = dalloc(c, &c->s.X[1], n);
+        if (rc == DI_OK) rc = dalloc(c, (char **)&c->s.XT[0], n * T);
+        if (rc == DI_OK) rc = dalloc(c, (char **)&c->s.XT[1], n * T);
+        if (rc == DI_OK) rc = dalloc(c, &c->s.pctl, 1);
+        if (rc != DI_OK) {
+            free_group(&c->s.X[0], &c->s.X[1], &c->s.XT[0], &c->s.XT[1], &c->s.pctl);
+            return rc;
+        }
         c->pi_ready = true;
     }
     if (c->gexec && c->gexec_kind == 1) {
@@ -1348,6 +1526,13 @@ int di_power(di_ctx *c, double tol, di_stats *st) {
         DI_TRY(enqueue_chunk(c, 1));
         DI_TRY(sync_ctl(c, c->s.pctl));
         const DevCtl &h = *c->h_ctl;
+        if (log_on()) {
+            di_stats ls{};
+            fill_stats(&ls, h, before, c->d, c->p.K, 0.0f, true);
+            ls.edge_updates = (int64_t)((h.sweep - before.sweep) * c->g.m);
+            ls.node_updates = (int64_t)((h.sweep - before.sweep) * n);
+            log_record(c, c->n_user, "power", "sync", h.sweep, ls, nullptr);
+        }
         if (c->o.timing && c->o.loop_mode == DI_LOOP_STREAM) DI_TRY(collect_timing(c, h.sweep - s0));
         if (h.done || h.overflow || h.sweep >= h.budget) break;
     }
@@ -1526,7 +1711,7 @@ int read_union(di_ctx *c, int what, void *dst, int on_device) {
             scale = c->d_gscale;
         }
         double *out = (double *)dst;
-        if (!on_device) DI_HIP(hipMalloc((void **)&out, sizeof(double) * nu));
+        if (!on_device) DI_HIP(dev_malloc((void **)&out, sizeof(double) * nu));
         const unsigned grid = grid_for(nu, 256, 16384);
         if (what == DI_F && c->p.fp32)
             k_unpad<float><<<grid, 256, 0, c->st>>>((const float *)c->s.F, nu, c->d_gp, c->d_gs, nullptr, G, out);
@@ -1536,7 +1721,7 @@ int read_union(di_ctx *c, int what, void *dst, int on_device) {
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && !on_device) e = hipMemcpyAsync(dst, out, sizeof(double) * nu, hipMemcpyDeviceToHost, c->st);
         if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-        if (!on_device) (void)hipFree(out);
+        if (!on_device) (void)dev_free(out);
         if (e != hipSuccess) DI_FAIL(DI_EHIP, "read failed: %s", hipGetErrorString(e));
         return DI_OK;
     }
@@ -1599,7 +1784,7 @@ int di_read(di_ctx *c, int what, void *dst, int on_device) {
     auto via_temp = [&](auto fill) -> int {  // produce doubles on the device, then copy
         double *tmp = nullptr;
         if (on_device) return fill((double *)dst);
-        DI_HIP(hipMalloc((void **)&tmp, sizeof(double) * std::max<i64>(n, 1)));
+        DI_HIP(dev_malloc((void **)&tmp, sizeof(double) * std::max<i64>(n, 1)));
         int rc = fill(tmp);
         if (rc == DI_OK) {
             hipError_t e = hipMemcpyAsync(dst, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, c->st);
@@ -1609,7 +1794,7 @@ int di_read(di_ctx *c, int what, void *dst, int on_device) {
                 rc = DI_EHIP;
             }
         }
-        (void)hipFree(tmp);
+        (void)dev_free(tmp);
         return rc;
     };
     switch (what) {
@@ -1667,7 +1852,8 @@ int di_read(di_ctx *c, int what, void *dst, int on_device) {
     }
 }
 
-int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *dw, int on_device, di_stats *st) {
+static int adjoint_call(di_ctx *c, const double *g, double tol_inf, double *dZ, double *dw, int on_device,
+                        di_stats *st) {
     if (!c) DI_FAIL(DI_EINVAL, "ctx is NULL");
     if (!g || !dZ) DI_FAIL(DI_EINVAL, "g and dZ must not be NULL");
     if (!(tol_inf > 0.0) || !std::isfinite(tol_inf)) DI_FAIL(DI_EINVAL, "tol_inf must be finite and > 0");
@@ -1675,12 +1861,16 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     if (!c->forward_converged) DI_FAIL(DI_ESTATE, "di_adjoint needs a converged di_diffuse first");
     const i64 n = c->g.n;
     if (!c->lam) {
-        DI_TRY(dalloc(c, &c->lam, n));
-        DI_TRY(dalloc(c, &c->aF, n));
-        DI_TRY(dalloc(c, &c->asnap, n));
-        DI_TRY(dalloc(c, &c->aZ, n));
-        DI_TRY(dalloc(c, &c->achk, 2));
-        DI_TRY(dalloc(c, &c->actl, 1));
+        int rc = dalloc(c, &c->lam, n);
+        if (rc == DI_OK) rc = dalloc(c, &c->aF, n);
+        if (rc == DI_OK) rc = dalloc(c, &c->asnap, n);
+        if (rc == DI_OK) rc = dalloc(c, &c->aZ, n);
+        if (rc == DI_OK) rc = dalloc(c, &c->achk, 2);
+        if (rc == DI_OK) rc = dalloc(c, &c->actl, 1);
+        if (rc != DI_OK) {
+            free_group(&c->lam, &c->aF, &c->asnap, &c->aZ, &c->achk, &c->actl);
+            return rc;
+        }
     }
     const i64 nu = c->n_user;  // the caller's node count (n is internal)
     // g checked on the device: a host g goes to the snapshot buffer (free until the sweeps
@@ -1731,6 +1921,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
             }
             DI_TRY(sync_ctl(c, c->actl));
             const DevCtl &h = *c->h_ctl;
+            log_adjoint_sync(c, h, before);
             if (h.done || h.overflow || h.sweep >= h.budget) break;
         }
     } else {
@@ -1740,6 +1931,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         // partials (max |F| as the sweep began, in-flight fluid delivered) meet the
         // tolerance, a delivery-only pass measures the state the call returns.
         if (!c->gT_ready) {
+            free_graph(c->gT);  // a build never starts over arrays it would not free
             c->gT.n = n;
             c->gT.m = c->g.m;
             c->gT.weighted = c->g.weighted;
@@ -1748,16 +1940,20 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
                 free_graph(c->gT);
                 return brc;
             }
+            c->gT_ready = true;
         }
         // in-flight buffers of double fluid (whatever the forward fluid type): n values,
         // then the bitmap of the nonzero ones
         const i64 s_vals = ((i64)(n * 8) + 255) & ~(i64)255;
         const i64 s_bytes = s_vals + ((n + 63) / 64) * 8;
         if (!c->aS[0]) {
-            DI_TRY(dalloc(c, (char **)&c->aS[0], s_bytes));
-            DI_TRY(dalloc(c, (char **)&c->aS[1], s_bytes));
+            int rc = dalloc(c, (char **)&c->aS[0], s_bytes);
+            if (rc == DI_OK) rc = dalloc(c, (char **)&c->aS[1], s_bytes);
+            if (rc != DI_OK) {
+                free_group(&c->aS[0], &c->aS[1]);
+                return rc;
+            }
         }
-        c->gT_ready = true;
         SolveState as;
         as.F = c->aF;
         as.H = c->lam;
@@ -1779,6 +1975,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
                 DI_TRY(launch_finalize(c->actl, ap, FIN_ADJ, c->st, as.partR, as.nR, as.partC, as.nC));
             }
             DI_TRY(sync_ctl(c, c->actl));
+            log_adjoint_sync(c, *c->h_ctl, before);
             if (c->h_ctl->overflow) break;
             if (c->h_ctl->done) {
                 DI_TRY(launch_adj_bld_sweep(c->gT, c->g.inv_s, as, ap, 0, c->st));
@@ -1800,7 +1997,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
     const bool zbuf = !on_device || c->seg, wbuf = !on_device && dw;
     if (zbuf) ddZ = tZ = c->aZ;
     if (wbuf) {
-        if (hipMalloc((void **)&tw, sizeof(double) * std::max<i64>(c->g.m, 1)) != hipSuccess)
+        if (dev_malloc((void **)&tw, sizeof(double) * std::max<i64>(c->g.m, 1)) != hipSuccess)
             DI_FAIL(DI_ENOMEM, "device allocation for the gradients failed");
         ddw = tw;
     }
@@ -1824,7 +2021,7 @@ int di_adjoint(di_ctx *c, const double *g, double tol_inf, double *dZ, double *d
         hipMemcpyAsync(dw, tw, sizeof(double) * c->g.m, hipMemcpyDeviceToHost, c->st) != hipSuccess)
         rc = DI_EHIP;
     if (hipStreamSynchronize(c->st) != hipSuccess) rc = DI_EHIP;
-    if (tw) (void)hipFree(tw);
+    if (tw) (void)dev_free(tw);
     if (rc != DI_OK) DI_FAIL(rc, "adjoint gradient step failed");
     if (!on_device) std::memcpy(dZ, hz.data(), sizeof(double) * nu);
     DI_TRY(sync_ctl(c, c->actl));
@@ -1874,16 +2071,16 @@ int di_update(di_ctx *c, const di_csr *g) {
     u64 *maxbits = nullptr;
     auto release = [&]() {
         for (void *q : {(void *)tH, (void *)tF, (void *)tP, (void *)w0, (void *)w1, (void *)w2, (void *)maxbits})
-            if (q) (void)hipFree(q);
+            if (q) (void)dev_free(q);
         if (c2) di_destroy(c2);
     };
     auto body = [&]() -> int {
-        DI_HIP(hipMalloc((void **)&tH, sizeof(double) * nu));
-        DI_HIP(hipMalloc((void **)&tF, sizeof(double) * nu));
-        DI_HIP(hipMalloc((void **)&tP, sizeof(double) * nu));
-        DI_HIP(hipMalloc((void **)&w0, sizeof(double) * n));
-        DI_HIP(hipMalloc((void **)&w1, sizeof(double) * n));
-        DI_HIP(hipMalloc((void **)&maxbits, sizeof(u64)));
+        DI_HIP(dev_malloc((void **)&tH, sizeof(double) * nu));
+        DI_HIP(dev_malloc((void **)&tF, sizeof(double) * nu));
+        DI_HIP(dev_malloc((void **)&tP, sizeof(double) * nu));
+        DI_HIP(dev_malloc((void **)&w0, sizeof(double) * n));
+        DI_HIP(dev_malloc((void **)&w1, sizeof(double) * n));
+        DI_HIP(dev_malloc((void **)&maxbits, sizeof(u64)));
         auto to_caller = [&](const double *src, double *dst) -> int {
             if (c->seg) {
                 k_seg_to_caller<<<grid_for(n, 256, 16384), 256, 0, c->st>>>(src, dst, c->d_seg_start, c->seg_rb, n);
@@ -1909,8 +2106,8 @@ int di_update(di_ctx *c, const di_csr *g) {
             seg_compact(c, zi.data(), zc.data());
         }
         DI_HIP(hipStreamSynchronize(c->st));
-        (void)hipFree(w0);
-        (void)hipFree(w1);
+        (void)dev_free(w0);
+        (void)dev_free(w1);
         w0 = w1 = nullptr;
         // the new graph, with the same d, Z and options (its own layout and row blocks)
         di_opts o = c->o;
@@ -1919,9 +2116,9 @@ int di_update(di_ctx *c, const di_csr *g) {
         o.graph_ptr = nullptr;
         DI_TRY(di_init(&c2, g, c->d, c->s.Z ? zc.data() : nullptr, &o));
         const i64 n2 = c2->g.n;
-        DI_HIP(hipMalloc((void **)&w0, sizeof(double) * n2));
-        DI_HIP(hipMalloc((void **)&w1, sizeof(double) * n2));
-        DI_HIP(hipMalloc((void **)&w2, sizeof(double) * n2));
+        DI_HIP(dev_malloc((void **)&w0, sizeof(double) * n2));
+        DI_HIP(dev_malloc((void **)&w1, sizeof(double) * n2));
+        DI_HIP(dev_malloc((void **)&w2, sizeof(double) * n2));
         auto from_caller = [&](const double *src, double *dst) -> int {
             if (c2->seg) {
                 k_caller_to_seg<<<grid_for(n2, 256, 16384), 256, 0, c2->st>>>(src, dst, c2->d_seg_start, c2->seg_rb, n2);
@@ -2050,7 +2247,12 @@ int di_load(di_ctx *c, const char *path) {
 }
 
 int di_info(di_ctx *c, int key, int64_t *value) {
-    if (!c || !value) DI_FAIL(DI_EINVAL, "NULL argument");
+    if (!value) DI_FAIL(DI_EINVAL, "NULL argument");
+    if (key == DI_INFO_LIVE_ALLOCATIONS) {  // process-wide: ctx may be NULL
+        *value = dev_live_allocations();
+        return DI_OK;
+    }
+    if (!c) DI_FAIL(DI_EINVAL, "NULL argument");
     switch (key) {
     case DI_INFO_N: *value = c->n_user; return DI_OK;
     case DI_INFO_N_INTERNAL: *value = c->g.n; return DI_OK;

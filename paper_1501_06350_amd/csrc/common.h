@@ -40,6 +40,14 @@ void set_error(const char *fmt, ...);
 
 #define DI_LAUNCH_CHECK() DI_HIP(hipGetLastError())
 
+// Every device allocation of the library goes through these two.  They keep the
+// process-wide count of live allocations, and inject a failure for tests of the error
+// paths: with DI_FAIL_ALLOC_AT=k in the environment, the k-th allocation after the
+// variable took its current value fails as out of memory without allocating.
+hipError_t dev_malloc(void **p, size_t bytes);
+hipError_t dev_free(void *p);
+long long dev_live_allocations();
+
 inline unsigned grid_for(i64 work, int per_block, i64 cap = (1ll << 30)) {
     i64 g = (work + per_block - 1) / per_block;
     if (g < 1) g = 1;

@@ -4,6 +4,7 @@
 #include "graph.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace di {
 
@@ -415,15 +416,38 @@ template <typename T>
 static int dalloc(T **p, i64 count) {
     *p = nullptr;
     if (count <= 0) count = 1;
-    DI_HIP(hipMalloc((void **)p, (size_t)count * sizeof(T)));
+    DI_HIP(dev_malloc((void **)p, (size_t)count * sizeof(T)));
     return DI_OK;
 }
+
+// device temporaries of one build, freed on every way out of it
+struct DevTemps {
+    std::vector<void *> p;
+    DevTemps() = default;
+    DevTemps(const DevTemps &) = delete;
+    DevTemps &operator=(const DevTemps &) = delete;
+    ~DevTemps() {
+        for (void *q : p)
+            if (q) (void)dev_free(q);
+    }
+    template <typename T>
+    int alloc(T **x, i64 count) {
+        DI_TRY(dalloc(x, count));
+        p.push_back((void *)*x);
+        return DI_OK;
+    }
+    void release(const void *q) {  // ownership passed on
+        for (void *&e : p)
+            if (e == q) e = nullptr;
+    }
+};
 
 int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const float *d_w, int range_log2,
                 bool remote_by_source,
                 hipStream_t st) {
     const i64 n = g.n, m = g.m;
     const int TB = 256;
+    DevTemps tmp;
     int key_bits = 0;
     while (((i64)1 << key_bits) < n) ++key_bits;
 
@@ -431,14 +455,14 @@ int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const f
     unsigned *keys = nullptr, *keys2 = nullptr;
     u64 *vals = nullptr, *vals2 = nullptr;
     i64 *counts = nullptr, *stemp = nullptr;
-    DI_TRY(dalloc(&keys, m));
-    DI_TRY(dalloc(&keys2, m));
-    DI_TRY(dalloc(&vals, m));
-    DI_TRY(dalloc(&vals2, m));
+    DI_TRY(tmp.alloc(&keys, m));
+    DI_TRY(tmp.alloc(&keys2, m));
+    DI_TRY(tmp.alloc(&vals, m));
+    DI_TRY(tmp.alloc(&vals2, m));
     const i64 ccount = radix_counts_elems(m);
     i64 scount = std::max(ccount, m + 1);
-    DI_TRY(dalloc(&counts, std::max(ccount, m + 1)));
-    DI_TRY(dalloc(&stemp, scan_temp_elems(scount) + 64));
+    DI_TRY(tmp.alloc(&counts, std::max(ccount, m + 1)));
+    DI_TRY(tmp.alloc(&stemp, scan_temp_elems(scount) + 64));
     k_expand_sources<<<grid_for(n, TB), TB, 0, st>>>(d_out_ptr, d_out_idx, d_w, n, keys, vals);
     DI_LAUNCH_CHECK();
     bool in_tmp = false;
@@ -467,8 +491,8 @@ int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const f
     g.rb = rb;
     g.nranges = (n + ((i64)1 << rb) - 1) >> rb;
     i64 *loc_deg = nullptr, *loc_first = nullptr;
-    DI_TRY(dalloc(&loc_deg, n + 1));
-    DI_TRY(dalloc(&loc_first, n));
+    DI_TRY(tmp.alloc(&loc_deg, n + 1));
+    DI_TRY(tmp.alloc(&loc_first, n));
     DI_TRY(dalloc(&g.rw, n));
     k_local_span<<<grid_for(n, TB), TB, 0, st>>>(d_out_ptr, d_out_idx, d_w, n, rb, loc_deg, loc_first, g.rw);
     DI_LAUNCH_CHECK();
@@ -530,29 +554,23 @@ int build_graph(DevGraph &g, const i64 *d_out_ptr, const int *d_out_idx, const f
         int *src2 = nullptr;
         unsigned short *tgt2 = nullptr;
         float *w2 = nullptr;
-        DI_TRY(dalloc(&src2, mr));
-        DI_TRY(dalloc(&tgt2, mr));
-        if (g.weighted) DI_TRY(dalloc(&w2, mr));
+        DI_TRY(tmp.alloc(&src2, mr));
+        DI_TRY(tmp.alloc(&tgt2, mr));
+        if (g.weighted) DI_TRY(tmp.alloc(&w2, mr));
         k_permute_remote<<<grid_for(mr, TB), TB, 0, st>>>(perm, mr, g.rem_src, g.rem_tgt, g.rem_w, src2, tgt2, w2);
         DI_LAUNCH_CHECK();
         DI_HIP(hipStreamSynchronize(st));
-        (void)hipFree(g.rem_src);
-        (void)hipFree(g.rem_tgt);
-        if (g.rem_w) (void)hipFree(g.rem_w);
+        (void)dev_free(g.rem_src);
+        (void)dev_free(g.rem_tgt);
+        if (g.rem_w) (void)dev_free(g.rem_w);
+        tmp.release(src2);
+        tmp.release(tgt2);
+        tmp.release(w2);
         g.rem_src = src2;
         g.rem_tgt = tgt2;
         g.rem_w = w2;
     }
     DI_HIP(hipStreamSynchronize(st));
-
-    (void)hipFree(keys);
-    (void)hipFree(keys2);
-    (void)hipFree(vals);
-    (void)hipFree(vals2);
-    (void)hipFree(counts);
-    (void)hipFree(stemp);
-    (void)hipFree(loc_deg);
-    (void)hipFree(loc_first);
     return DI_OK;
 }
 
@@ -561,7 +579,7 @@ void free_graph(DevGraph &g) {
                   g.rem_src, g.rem_tgt, g.rem_w, g.rem_base, g.loc_base, g.out_ptr, g.out_idx, g.w,
                   g.deg_flags};
     for (void *p : ps)
-        if (p) (void)hipFree(p);
+        if (p) (void)dev_free(p);
     g = DevGraph{};
 }
 

@@ -1690,12 +1690,12 @@ int build_row_blocks(RowBlocks &rb, const i64 *d_ptr, i64 n, hipStream_t st) {
     start.push_back(n);
     rb.nrb = (i64)sf.size();
     rb.nseg = (i64)sb.size();
-    DI_HIP(hipMalloc((void **)&rb.start, sizeof(i64) * start.size()));
-    DI_HIP(hipMalloc((void **)&rb.seg_first, sizeof(int) * std::max<size_t>(sf.size(), 1)));
-    DI_HIP(hipMalloc((void **)&rb.seg_count, sizeof(int) * std::max<size_t>(sc.size(), 1)));
-    DI_HIP(hipMalloc((void **)&rb.seg_b, sizeof(i64) * std::max<size_t>(sb.size(), 1)));
-    DI_HIP(hipMalloc((void **)&rb.seg_e, sizeof(i64) * std::max<size_t>(se.size(), 1)));
-    DI_HIP(hipMalloc((void **)&rb.partial, sizeof(double) * std::max<size_t>(sb.size(), 1)));
+    DI_HIP(dev_malloc((void **)&rb.start, sizeof(i64) * start.size()));
+    DI_HIP(dev_malloc((void **)&rb.seg_first, sizeof(int) * std::max<size_t>(sf.size(), 1)));
+    DI_HIP(dev_malloc((void **)&rb.seg_count, sizeof(int) * std::max<size_t>(sc.size(), 1)));
+    DI_HIP(dev_malloc((void **)&rb.seg_b, sizeof(i64) * std::max<size_t>(sb.size(), 1)));
+    DI_HIP(dev_malloc((void **)&rb.seg_e, sizeof(i64) * std::max<size_t>(se.size(), 1)));
+    DI_HIP(dev_malloc((void **)&rb.partial, sizeof(double) * std::max<size_t>(sb.size(), 1)));
     DI_HIP(hipMemcpyAsync(rb.start, start.data(), sizeof(i64) * start.size(), hipMemcpyHostToDevice, st));
     if (!sf.empty()) {
         DI_HIP(hipMemcpyAsync(rb.seg_first, sf.data(), sizeof(int) * sf.size(), hipMemcpyHostToDevice, st));
@@ -1712,7 +1712,7 @@ int build_row_blocks(RowBlocks &rb, const i64 *d_ptr, i64 n, hipStream_t st) {
 void free_row_blocks(RowBlocks &rb) {
     void *ps[] = {rb.start, rb.seg_first, rb.seg_count, rb.seg_b, rb.seg_e, rb.partial};
     for (void *p : ps)
-        if (p) (void)hipFree(p);
+        if (p) (void)dev_free(p);
     rb = RowBlocks{};
 }
 

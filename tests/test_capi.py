@@ -166,3 +166,14 @@ def test_null_arguments(lib):
     assert lib.di_save(None, None) == binding.DI_EINVAL
     assert lib.di_load(None, None) == binding.DI_EINVAL
     assert lib.di_destroy(None) == binding.DI_OK
+
+
+def test_live_allocations_needs_no_context(lib):
+    """The process-wide allocation count is the one info key that takes a NULL context
+    (and touches no device: nothing has been allocated in this process)."""
+    import ctypes
+    from paper_1501_06350_amd import binding
+    v = ctypes.c_int64(-1)
+    assert lib.di_info(None, binding.INFO_LIVE_ALLOCATIONS, ctypes.byref(v)) == binding.DI_OK
+    assert v.value == 0
+    assert lib.di_info(None, binding.INFO_N, ctypes.byref(v)) == binding.DI_EINVAL
