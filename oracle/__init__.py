@@ -39,9 +39,13 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        build_library()
-    lib = ctypes.CDLL(_LIB_PATH)
+    # DI_ORACLE_LIB names another build of the same source (the sanitizer test uses it)
+    path = os.environ.get("DI_ORACLE_LIB")
+    if not path:
+        if not os.path.exists(_LIB_PATH):
+            build_library()
+        path = _LIB_PATH
+    lib = ctypes.CDLL(path)
     i64, dbl, vp, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
     lib.or_build_in.argtypes = [i64, i64, vp, vp, vp, vp, vp]
     lib.or_inv_s.argtypes = [i64, vp, vp, vp]

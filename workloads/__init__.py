@@ -44,9 +44,13 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        build_library()
-    lib = ctypes.CDLL(_LIB_PATH)
+    # DI_WEBGEN_LIB names another build of the same source (the sanitizer test uses it)
+    path = os.environ.get("DI_WEBGEN_LIB")
+    if not path:
+        if not os.path.exists(_LIB_PATH):
+            build_library()
+        path = _LIB_PATH
+    lib = ctypes.CDLL(path)
     i64, u64, dbl, vp = ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
     lib.wl_hash.restype = u64
     lib.wl_hash.argtypes = [u64, u64, u64, u64]
