@@ -171,6 +171,8 @@ def main():
     ap.add_argument("--tile-only", action="store_true",
                     help="for profiling: only the k=64 tile solve with --tile-theta / --tile-rounds, stream and "
                          "graph loop modes")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="for profiling: only the adjoint leg (weighted webgen(2M)), printed as one JSON line")
     ap.add_argument("--tile-theta", type=float, default=1.0)
     ap.add_argument("--tile-rounds", type=int, default=2)
     args = ap.parse_args()
@@ -192,6 +194,9 @@ def main():
         return
     if args.curves:
         print(json.dumps({"convergence": cpu_baseline_curves(args.curve_rounds, args.theta, args.rounds)}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": bench_adjoint()}), flush=True)
         return
     if args.tile_only:
         print(json.dumps({"tile": bench_tile_only(args.tile_theta, args.tile_rounds)}), flush=True)
