@@ -3,6 +3,7 @@
 injected device-allocation failures (DI_FAIL_ALLOC_AT) at every allocation of a context's
 life: each failing call returns DI_ENOMEM, frees what it had allocated, and a retry of the
 same call succeeds with the oracle's result."""
+import gc
 import json
 
 import numpy as np
@@ -85,6 +86,7 @@ def test_injected_allocation_failures_free_everything(gpu, monkeypatch):
     c = W.normal_vector(g.n, 2)
     lam_o, _, _, conv = O.adjoint(og, D, c, tol_inf=1e-14)
     assert conv
+    gc.collect()  # contexts other tests left to the collector are closed before the count is taken
     base = gpu.live_allocations()
     failures = {}
     for k in range(1, 1000):
