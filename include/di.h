@@ -21,12 +21,13 @@
  *
  * Environment (read at each use):
  *   DI_LOG=path          append JSON lines to path: one per host synchronisation of
- *                        di_diffuse, di_power and di_adjoint (every sweeps_per_sync sweeps;
- *                        1 gives one per sweep: sweep index, the call's sweeps, node and
- *                        edge updates and DI rounds so far, residual, bounds, leak, host
- *                        ms) and one at the end of each such call (plus status,
- *                        converged, mass defect, device ms, GEUPS).  Best effort: a file
- *                        that cannot be opened is skipped, never an error.
+ *                        di_diffuse (contexts with k = 1), di_power and di_adjoint, that
+ *                        is every sweeps_per_sync sweeps (1 gives one per sweep): sweep
+ *                        index, the call's sweeps, node and edge updates and DI rounds so
+ *                        far, residual, bounds, leak, host ms; and one at the end of each
+ *                        such call (plus status, converged, mass defect, device ms,
+ *                        GEUPS; non-finite values as null).  Best effort: a file that
+ *                        cannot be opened is skipped, never an error.
  *   DI_FAIL_ALLOC_AT=k   for tests of the error paths: the k-th device allocation after
  *                        the variable took its current value fails as out of memory
  *                        (the call returns DI_ENOMEM and frees what it had allocated).

@@ -471,6 +471,15 @@ void log_line(const char *line) {
     fflush(g_log_file);
 }
 
+// a JSON number, or null for a value that is not finite (a run that overflowed)
+struct JNum {
+    char b[40];
+    explicit JNum(double v) {
+        if (std::isfinite(v)) snprintf(b, sizeof(b), "%.17g", v);
+        else snprintf(b, sizeof(b), "null");
+    }
+};
+
 void log_record(const di_ctx *c, i64 n, const char *call, const char *event, long long sweep, const di_stats &s,
                 const int *status) {
     if (!log_on()) return;
@@ -479,15 +488,15 @@ void log_record(const di_ctx *c, i64 n, const char *call, const char *event, lon
     char buf[1024];
     int k = snprintf(buf, sizeof(buf),
                      "{\"call\":\"%s\",\"event\":\"%s\",\"ctx\":\"%p\",\"sweep\":%lld,\"sweeps\":%lld,"
-                     "\"node_updates\":%lld,\"edge_updates\":%lld,\"rounds\":%.6g,\"residual\":%.17g,"
-                     "\"bound\":%.17g,\"bound_norm\":%.17g,\"leak\":%.17g,\"host_ms\":%.3f",
+                     "\"node_updates\":%lld,\"edge_updates\":%lld,\"rounds\":%.6g,\"residual\":%s,"
+                     "\"bound\":%s,\"bound_norm\":%s,\"leak\":%s,\"host_ms\":%.3f",
                      call, event, (const void *)c, sweep, (long long)s.sweeps, (long long)s.node_updates,
-                     (long long)s.edge_updates, n > 0 ? (double)s.node_updates / (double)n : 0.0, s.residual, s.bound,
-                     s.bound_norm, s.leak, host_ms);
+                     (long long)s.edge_updates, n > 0 ? (double)s.node_updates / (double)n : 0.0,
+                     JNum(s.residual).b, JNum(s.bound).b, JNum(s.bound_norm).b, JNum(s.leak).b, host_ms);
     if (status && k > 0 && k < (int)sizeof(buf))
         k += snprintf(buf + k, sizeof(buf) - k,
-                      ",\"status\":%d,\"converged\":%d,\"mass_defect\":%.17g,\"device_ms\":%.4f,\"geups\":%.6g",
-                      *status, s.converged, s.mass_defect, s.ms,
+                      ",\"status\":%d,\"converged\":%d,\"mass_defect\":%s,\"device_ms\":%.4f,\"geups\":%.6g",
+                      *status, s.converged, JNum(s.mass_defect).b, s.ms,
                       s.ms > 0 ? (double)s.edge_updates / (s.ms * 1e6) : 0.0);
     if (k > 0 && k < (int)sizeof(buf) - 2) {
         buf[k] = '}';
@@ -1329,7 +1338,8 @@ static int adjoint_call(di_ctx *c, const double *g, double tol_inf, double *dZ, 
 
 // the end record of DI_LOG for a finished call (stats from the call, or zeros)
 static void log_end(di_ctx *c, const char *call, const di_stats &s, int rc) {
-    if (c && log_on()) log_record(c, c->n_user, call, "end", c->h_ctl ? c->h_ctl->sweep : -1, s, &rc);
+    // the single-column control block's sweep index (-1 for the k-column tile, which keeps its own)
+    if (c && log_on()) log_record(c, c->n_user, call, "end", c->h_ctl && !c->b ? c->h_ctl->sweep : -1, s, &rc);
 }
 
 static void log_adjoint_sync(di_ctx *c, const DevCtl &h, const DevCtl &before) {
