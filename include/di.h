@@ -82,7 +82,11 @@ typedef struct {
  *                    (the DI-argmax rule of Section 3.4 applied per sweep) [1.0]
  *   max_sweeps     : sweep (or iteration) budget per di_diffuse / di_power call [100000]
  *   deterministic  : 1 = synchronous sweeps with snapshot semantics and ordered
- *                    accumulation (bit-reproducible, slower) [0]
+ *                    accumulation (bit-reproducible, slower) [0].  This is also the
+ *                    scatter strategy: 0 pushes inside a block-local range with LDS
+ *                    atomic adds and pulls cross-range fluid through a layout sorted by
+ *                    target (no atomics in memory); 1 snapshots the active set and pulls
+ *                    along IN rows in row order (no atomics at all)
  *   range_log2     : block-local range size 2^range_log2 nodes, 8..13 (0 = auto).
  *                    With k > 1: 6..8 runs the tile's block-local sweep (auto: the
  *                    largest range whose fluid tile lets two workgroups share a compute
