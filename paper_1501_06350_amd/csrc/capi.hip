@@ -206,6 +206,97 @@ int make_range_order(di_ctx *c, const DevGraph &g, int **out) {
     return DI_OK;
 }
 
+// Checks of a graph held on the device, the rules of validate_host_csr: out[0] = n - i for
+// the first row i that ends before it starts, out[1] = m - p for the first target out of
+// range, out[2] = m - p for the first weight that is not finite and > 0, out[3] = 1 when
+// some row is not sorted by target (out starts at zero).  Row bounds are clamped to
+// [0, m] before any edge is read, so a broken out_ptr reads nothing out of range.
+__global__ void __launch_bounds__(256) k_check_csr(const i64 *__restrict__ ptr, const int *__restrict__ idx,
+                                                   const float *__restrict__ w, i64 n, i64 m, u64 *out) {
+    __shared__ u64 red[3][256 / WAVE];
+    __shared__ unsigned uns_any;
+    if (threadIdx.x == 0) uns_any = 0;
+    __syncthreads();
+    u64 br = 0, bi = 0, bw = 0;
+    unsigned uns = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const i64 b = ptr[i], e = ptr[i + 1];
+        if (e < b) br = max(br, (u64)(n - i));
+        const i64 bb = min(max(b, (i64)0), m), ee = min(max(e, (i64)0), m);
+        for (i64 p = bb; p < ee; ++p) {
+            const int t = idx[p];
+            if (t < 0 || (i64)t >= n) bi = max(bi, (u64)(m - p));
+            if (p > bb && idx[p - 1] > t) uns = 1;
+            if (w) {
+                const float x = w[p];
+                if (!(x > 0.0f) || !__builtin_isfinite(x)) bw = max(bw, (u64)(m - p));
+            }
+        }
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        br = max(br, (u64)__shfl_xor((unsigned long long)br, o, WAVE));
+        bi = max(bi, (u64)__shfl_xor((unsigned long long)bi, o, WAVE));
+        bw = max(bw, (u64)__shfl_xor((unsigned long long)bw, o, WAVE));
+    }
+    const int wv = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        red[0][wv] = br;
+        red[1][wv] = bi;
+        red[2][wv] = bw;
+    }
+    if (uns) atomicOr(&uns_any, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {  // one atomic per block and value
+        for (int k = 1; k < 256 / WAVE; ++k) {
+            br = max(br, red[0][k]);
+            bi = max(bi, red[1][k]);
+            bw = max(bw, red[2][k]);
+        }
+        if (br) atomicMax((unsigned long long *)&out[0], (unsigned long long)br);
+        if (bi) atomicMax((unsigned long long *)&out[1], (unsigned long long)bi);
+        if (bw) atomicMax((unsigned long long *)&out[2], (unsigned long long)bw);
+        if (uns_any) atomicOr((unsigned long long *)&out[3], 1ull);
+    }
+}
+
+// validate_host_csr for a graph whose arrays are on the device; nothing is copied to the
+// host but the verdict (and the values an error message names)
+int validate_device_csr(const di_csr *g, hipStream_t st, bool *sorted) {
+    const i64 n = g->n, m = g->m;
+    i64 ends[2] = {0, 0};
+    DI_HIP(hipMemcpy(&ends[0], g->out_ptr, sizeof(i64), hipMemcpyDeviceToHost));
+    DI_HIP(hipMemcpy(&ends[1], g->out_ptr + n, sizeof(i64), hipMemcpyDeviceToHost));
+    if (ends[0] != 0) DI_FAIL(DI_EINVAL, "out_ptr[0] must be 0");
+    if (ends[1] != m) DI_FAIL(DI_EINVAL, "out_ptr[n] (%lld) must equal m (%lld)", (long long)ends[1], (long long)m);
+    u64 *d_out = nullptr;
+    DI_HIP(dev_malloc((void **)&d_out, 4 * sizeof(u64)));
+    u64 h[4] = {0, 0, 0, 0};
+    hipError_t e = launch_fill_zero(d_out, 4 * sizeof(u64), st) == DI_OK ? hipSuccess : hipErrorLaunchFailure;
+    if (e == hipSuccess) {
+        k_check_csr<<<grid_for(n, 256, 4096), 256, 0, st>>>(g->out_ptr, g->out_idx, g->w, n, m, d_out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)dev_free(d_out);
+    if (e != hipSuccess) DI_FAIL(DI_EHIP, "graph check on the device failed: %s", hipGetErrorString(e));
+    if (h[0]) DI_FAIL(DI_EINVAL, "out_ptr not non-decreasing at row %lld", (long long)(n - (i64)h[0]));
+    if (h[1]) {
+        const i64 p = m - (i64)h[1];
+        int t = 0;
+        DI_HIP(hipMemcpy(&t, g->out_idx + p, sizeof(int), hipMemcpyDeviceToHost));
+        DI_FAIL(DI_EINVAL, "out_idx[%lld] = %d out of range [0, %lld)", (long long)p, t, (long long)n);
+    }
+    if (h[2]) {
+        const i64 p = m - (i64)h[2];
+        float x = 0.0f;
+        DI_HIP(hipMemcpy(&x, g->w + p, sizeof(float), hipMemcpyDeviceToHost));
+        DI_FAIL(DI_EINVAL, "w[%lld] = %g must be > 0 and finite", (long long)p, (double)x);
+    }
+    *sorted = h[3] == 0;
+    return DI_OK;
+}
+
 int validate_host_csr(const di_csr *g, bool *sorted) {
     const i64 n = g->n, m = g->m;
     if (g->out_ptr[0] != 0) DI_FAIL(DI_EINVAL, "out_ptr[0] must be 0");
@@ -671,8 +762,8 @@ int upload_segmented(di_ctx *c, const i64 *ptr, const int *idx, const float *w, 
         !hip_ok(dev_malloc((void **)&diff, sizeof(i64) * (n + 2))) ||
         !hip_ok(dev_malloc((void **)&excl, sizeof(i64) * (n + 2))) ||
         !hip_ok(dev_malloc((void **)&temp, sizeof(i64) * (scan_temp_elems(n + 2) + 64))) ||
-        !hip_ok(hipMemcpy(d_ptr, ptr, sizeof(i64) * (n + 1), hipMemcpyHostToDevice)) ||
-        (m && !hip_ok(hipMemcpy(d_idx, idx, sizeof(int) * m, hipMemcpyHostToDevice)))) {
+        !hip_ok(hipMemcpy(d_ptr, ptr, sizeof(i64) * (n + 1), hipMemcpyDefault)) ||
+        (m && !hip_ok(hipMemcpy(d_idx, idx, sizeof(int) * m, hipMemcpyDefault)))) {
         cleanup();
         if (d_idx) (void)dev_free(d_idx);
         return hip_code();
@@ -958,7 +1049,15 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     const i64 *ptr = g->out_ptr;
     const int *idx = g->out_idx;
     const float *w = g->w;
-    if (g->on_device) {
+    // a graph on the device with rows sorted by target is checked there and copied device
+    // to device; a union of graphs (relabelled on the host) or unsorted rows take the host path
+    bool checked = false;
+    if (g->on_device && opt.n_graphs <= 1) {
+        bool sorted_dev = false;
+        DI_TRY(validate_device_csr(g, (hipStream_t)opt.stream, &sorted_dev));
+        checked = sorted_dev;
+    }
+    if (g->on_device && !checked) {
         hptr.resize((size_t)n + 1);
         hidx.resize((size_t)std::max<i64>(m, 1));
         DI_HIP(hipMemcpy(hptr.data(), g->out_ptr, sizeof(i64) * (n + 1), hipMemcpyDeviceToHost));
@@ -976,7 +1075,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     hv.out_idx = idx;
     hv.w = w;
     bool sorted = true;
-    DI_TRY(validate_host_csr(&hv, &sorted));
+    if (!checked) DI_TRY(validate_host_csr(&hv, &sorted));
     if (!sorted) {
         if (hidx.empty()) hidx.assign(idx, idx + m);
         if (w && hw.empty()) hw.assign(w, w + m);
@@ -1100,7 +1199,7 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         const i64 X = std::min<i64>(opt.range_cut == 0 ? 1024 : opt.range_cut, B / 2);
         if ((rc = upload_segmented(c, ptr, idx, w, n, m, rb, X)) != DI_OK) return fail(rc);
         if (w && (rc = dalloc(c, &c->g.w, m))) return fail(rc);
-        if (w && m && hipMemcpy(c->g.w, w, sizeof(float) * m, hipMemcpyHostToDevice) != hipSuccess) {
+        if (w && m && hipMemcpy(c->g.w, w, sizeof(float) * m, hipMemcpyDefault) != hipSuccess) {
             set_error("upload of the weights failed");
             return fail(DI_EHIP);
         }
@@ -1115,9 +1214,9 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     } else {
         if ((rc = dalloc(c, &c->g.out_ptr, n + 1)) || (rc = dalloc(c, &c->g.out_idx, m))) return fail(rc);
         if (w && (rc = dalloc(c, &c->g.w, m))) return fail(rc);
-        if (hipMemcpy(c->g.out_ptr, ptr, sizeof(i64) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
-            (m && hipMemcpy(c->g.out_idx, idx, sizeof(int) * m, hipMemcpyHostToDevice) != hipSuccess) ||
-            (w && m && hipMemcpy(c->g.w, w, sizeof(float) * m, hipMemcpyHostToDevice) != hipSuccess)) {
+        if (hipMemcpy(c->g.out_ptr, ptr, sizeof(i64) * (n + 1), hipMemcpyDefault) != hipSuccess ||
+            (m && hipMemcpy(c->g.out_idx, idx, sizeof(int) * m, hipMemcpyDefault) != hipSuccess) ||
+            (w && m && hipMemcpy(c->g.w, w, sizeof(float) * m, hipMemcpyDefault) != hipSuccess)) {
             set_error("upload of the graph failed");
             return fail(DI_EHIP);
         }

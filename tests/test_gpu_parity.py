@@ -274,6 +274,53 @@ def test_device_inputs(gpu):
     s.close()
 
 
+def test_device_graph_is_checked_on_the_device(gpu):
+    """A graph given in device memory is checked there with the host check's rules and
+    messages, and solves bit for bit like the same graph given on the host (sorted rows are
+    copied device to device; unsorted rows are sorted on the host first)."""
+    import torch
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    g = W.webgen(5000, 3, weighted=True)
+    m = len(g.out_idx)
+    rng = np.random.default_rng(5)
+    rows = np.nonzero(np.diff(g.out_ptr) >= 3)[0]
+    shuffled = g.out_idx.copy()
+    for r in rows[:50]:
+        b, e = g.out_ptr[r], g.out_ptr[r + 1]
+        shuffled[b:e] = shuffled[b:e][rng.permutation(e - b)]
+    for idx in (g.out_idx, shuffled):  # the same arrays on the host and on the device
+        hs = {}
+        for where in ("host", "device"):
+            arrs = (g.out_ptr, idx, g.w) if where == "host" else (T(g.out_ptr), T(idx), T(g.w))
+            with gpu.Solver(g.n, *arrs, d=D, deterministic=True) as s:
+                s.diffuse(1e-12)
+                hs[where] = s.read(gpu.H)
+        assert np.array_equal(hs["host"], hs["device"])
+    base = gpu.live_allocations()
+    p_bad_first = g.out_ptr.copy(); p_bad_first[0] = 1
+    p_bad_last = g.out_ptr.copy(); p_bad_last[-1] = m - 1
+    r = int(rows[10])
+    p_bad_mid = g.out_ptr.copy(); p_bad_mid[r] = p_bad_mid[r + 1] + 1
+    i_big = g.out_idx.copy(); i_big[123] = g.n
+    i_neg = g.out_idx.copy(); i_neg[7] = -1
+    w_zero = g.w.copy(); w_zero[99] = 0.0
+    w_nan = g.w.copy(); w_nan[5] = np.nan
+    cases = [(p_bad_first, g.out_idx, g.w), (p_bad_last, g.out_idx, g.w), (p_bad_mid, g.out_idx, g.w),
+             (g.out_ptr, i_big, g.w), (g.out_ptr, i_neg, g.w), (g.out_ptr, g.out_idx, w_zero),
+             (g.out_ptr, g.out_idx, w_nan)]
+    for arrs in cases:
+        msgs = []
+        for on_dev in (False, True):
+            with pytest.raises(gpu.DIError) as e:
+                gpu.Solver(g.n, *[T(a) if on_dev else a for a in arrs], d=D)
+            assert e.value.code == gpu.DI_EINVAL
+            msgs.append(str(e.value))
+        say(msgs[1])
+        assert msgs[0] == msgs[1]
+        assert gpu.live_allocations() == base
+
+
 def test_error_paths(gpu):
     g = W.tiny_zipf(300, 3)
     with gpu.from_graph(g, d=D, max_sweeps=2) as s:
