@@ -173,6 +173,52 @@ def test_adjoint_rejects_non_finite_g(gpu, on_device):
         assert st["converged"] and np.abs(s.read(gpu.LAMBDA) - lam).max() <= 2e-11
 
 
+@pytest.mark.parametrize("case", ["zero_g", "edgeless", "single_loop", "multi_edges_w", "dangling_mass"])
+@pytest.mark.parametrize("det", [False, True])
+def test_adjoint_edge_cases(gpu, case, det):
+    """Degenerate adjoint inputs against the dense adjoint and the oracle's gradient formula:
+    a zero right-hand side (lambda = 0 at once), a graph without edges (lambda = g), a
+    single self-loop (lambda = g / (1 - d)), repeated weighted edges, and all of g on a
+    dangling node of a web graph."""
+    rng = np.random.default_rng(3)
+    if case == "edgeless":
+        g = W.from_edges(9, [], [])
+    elif case == "single_loop":
+        g = W.from_edges(1, [0], [0])
+    elif case == "multi_edges_w":
+        g = W.from_edges(5, [0, 0, 0, 1, 2, 3, 3], [1, 1, 1, 2, 0, 3, 3],
+                         np.array([0.5, 2.0, 1.0, 3.0, 1.0, 0.25, 4.0], dtype=np.float32))
+    else:
+        g = W.webgen(3000, 11)
+    og = O.OGraph.of(g)
+    c = np.zeros(g.n)
+    if case == "dangling_mass":
+        c[int(np.nonzero(og.dangling)[0][0])] = 1.0
+    elif case != "zero_g":
+        c = rng.standard_normal(g.n)
+    lam = O.dense_adjoint(og, D, c)
+    with gpu.from_graph(g, d=D, deterministic=det) as s:
+        s.diffuse(1e-13)
+        x = s.read(gpu.H)
+        dZ, dw, st = s.adjoint(c, 1e-13)
+        lg = s.read(gpu.LAMBDA)
+    assert st["converged"]
+    if case == "zero_g":
+        assert st["sweeps"] == 0 and not lg.any() and not dZ.any() and not dw.any()
+        return
+    scale = max(np.abs(lam).max(), 1e-300)
+    assert np.abs(lg - lam).max() <= 1e-12 * scale + st["bound"]
+    np.testing.assert_allclose(dZ, (1 - D) * lg, rtol=1e-15, atol=0)
+    dw_o, _ = O.edge_grad(og, D, x, lg)
+    assert len(dw) == g.m
+    if g.m:
+        assert np.abs(dw - dw_o).max() <= 1e-13 * max(np.abs(dw_o).max(), 1e-300) + 1e-16
+    if case == "edgeless":
+        assert np.abs(lg - c).max() <= 1e-15 * np.abs(c).max()
+    if case == "single_loop":
+        assert abs(lg[0] - c[0] / (1 - D)) <= 1e-12 * abs(c[0] / (1 - D))
+
+
 @pytest.fixture(scope="module")
 def fd_subgraph():
     g = W.webgen(2_000_000, 5, weighted=True)
