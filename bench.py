@@ -171,6 +171,10 @@ def main():
     ap.add_argument("--tile-only", action="store_true",
                     help="for profiling: only the k=64 tile solve with --tile-theta / --tile-rounds, stream and "
                          "graph loop modes")
+    ap.add_argument("--union-only", action="store_true",
+                    help="for profiling: only the 256-graph union leg, printed as one JSON line")
+    ap.add_argument("--update-only", action="store_true",
+                    help="for profiling: only the graph-update leg on webgen(--n, --seed) with --theta / --rounds")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="for profiling: only the adjoint leg (weighted webgen(2M)), printed as one JSON line")
     ap.add_argument("--tile-theta", type=float, default=1.0)
@@ -194,6 +198,13 @@ def main():
         return
     if args.curves:
         print(json.dumps({"convergence": cpu_baseline_curves(args.curve_rounds, args.theta, args.rounds)}), flush=True)
+        return
+    if args.union_only:
+        print(json.dumps({"union": bench_union()}), flush=True)
+        return
+    if args.update_only:
+        g = W.webgen(args.n, args.seed)
+        print(json.dumps({"update": bench_update(g, args.theta, args.rounds)}), flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": bench_adjoint()}), flush=True)
