@@ -63,6 +63,35 @@ def test_log_records_every_sweep_of_a_deterministic_solve(gpu, tmp_path, monkeyp
     assert all(a["residual"] >= b["residual"] for a, b in zip(psync, psync[1:]))
 
 
+def test_log_records_adjoint_and_union(gpu, tmp_path, monkeypatch):
+    """The adjoint's records carry its L-infinity bound (the last one meets the tolerance);
+    a union of graphs logs its sweeps and its end record like a single graph."""
+    path = str(tmp_path / "di.jsonl")
+    monkeypatch.setenv("DI_LOG", path)
+    g = W.webgen(20_000, 14, weighted=True)
+    c = W.normal_vector(g.n, 8)
+    with gpu.from_graph(g, d=D, sweeps_per_sync=2) as s:
+        s.diffuse(1e-11)
+        _, _, sta = s.adjoint(c, 1e-11)
+    u, gp = W.union([W.webgen(3000, 21), W.tiny_zipf(700, 22), W.from_edges(1, [], [])])
+    with gpu.Solver(u.n, u.out_ptr, u.out_idx, None, d=D, graph_ptr=gp, sweeps_per_sync=1) as su:
+        stu = su.diffuse(1e-9)
+    monkeypatch.delenv("DI_LOG")
+    recs = read_log(path)
+    adj = [r for r in recs if r["call"] == "adjoint"]
+    aend = [r for r in adj if r["event"] == "end"]
+    assert len(aend) == 1 and aend[0]["converged"] == 1 and aend[0]["sweeps"] == sta["sweeps"]
+    assert aend[0]["bound"] == sta["bound"] and aend[0]["bound"] <= 1e-11
+    asyncs = [r for r in adj if r["event"] == "sync"]
+    assert len(asyncs) >= 1 and all(r["call"] == "adjoint" for r in asyncs)
+    diff = [r for r in recs if r["call"] == "diffuse"]
+    uend = diff[-1]
+    assert uend["event"] == "end" and uend["converged"] == 1 and uend["sweeps"] == stu["sweeps"]
+    usync = [r for r in diff if r["event"] == "sync" and r["ctx"] == uend["ctx"]]
+    assert len(usync) == stu["sweeps"]
+    assert all(r["sweeps"] == t + 1 for t, r in enumerate(usync))
+
+
 def test_log_is_off_when_unset(gpu, tmp_path, monkeypatch):
     monkeypatch.delenv("DI_LOG", raising=False)
     g = W.tiny_zipf(2000, 3)
