@@ -1100,9 +1100,9 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
     }
 
     // block-local range size: unweighted graphs use the LDS-resident kernel with 2^11-node
-    // ranges; weighted graphs the largest range whose fluid fits in LDS; small graphs keep
-    // at least ~256 nodes per range so that several workgroups run
-    const int rbmax = 13;  // two 2^13-node double tiles of the weighted sweep fill its LDS
+    // ranges; weighted graphs 2^12-node ranges (two workgroups of the weighted sweep per
+    // compute unit); small graphs keep at least ~256 nodes per range so that several
+    // workgroups run
     int rb = opt.range_log2;
     if (rb == 0 && opt.k > 1 && !opt.deterministic) {
         // several columns: ranges whose k-column fluid tile and local edge lists fit in
@@ -1110,7 +1110,9 @@ int di_init(di_ctx **out, const di_csr *g, double d, const double *Z, const di_o
         rb = tile_range_log2(opt.k, opt.fluid_fp32, w != nullptr);
         if (rb == 0) rb = 8;
     } else if (rb == 0) {
-        const int cap = w ? rbmax : 11;
+        // weighted: the largest range that lets two workgroups of the weighted sweep share
+        // a compute unit (2^12 nodes)
+        const int cap = w ? 12 : 11;
         rb = 8;
         while (rb < cap && ((i64)1 << (rb + 1)) * 256 <= n) ++rb;
     }

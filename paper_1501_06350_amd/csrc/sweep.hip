@@ -21,7 +21,9 @@
 
 namespace di {
 
-constexpr int BLD_THREADS = 1024;
+// 12 waves: with 2^12-node ranges the LDS of two such workgroups fits one compute unit
+// (2 x 81.7 KB), so a CU runs 24 waves instead of one 16-wave workgroup
+constexpr int BLD_THREADS = 768;
 constexpr int BLD_WAVES = BLD_THREADS / WAVE;
 
 int bld_threads() { return BLD_THREADS; }
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(BLD_THREADS) k_bld_sweep(BldArgs a) {
     {
         // batches of REM_U entries per thread: all index loads, then all gathers, then
         // the LDS adds, so that each thread keeps REM_U independent loads in flight
-        constexpr int REM_U = 8;
+        constexpr int REM_U = 4;  // 8 would take the registers the second workgroup needs
         const i64 p0 = a.rem_base[r], p1 = a.rem_base[r + 1];
         for (i64 pb = p0 + threadIdx.x; pb < p1; pb += (i64)BLD_THREADS * REM_U) {
             // out-of-range slots re-read the last entry (a valid address) and add nothing

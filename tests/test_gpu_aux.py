@@ -84,10 +84,13 @@ def test_log_records_adjoint_and_union(gpu, tmp_path, monkeypatch):
     assert aend[0]["bound"] == sta["bound"] and aend[0]["bound"] <= 1e-11
     asyncs = [r for r in adj if r["event"] == "sync"]
     assert len(asyncs) >= 1 and all(r["call"] == "adjoint" for r in asyncs)
-    diff = [r for r in recs if r["call"] == "diffuse"]
+    # the union's records follow the adjoint's end record (a freed context's address may be
+    # reused, so the ctx field alone does not tell the two contexts apart)
+    after = recs[recs.index(aend[0]) + 1:]
+    diff = [r for r in after if r["call"] == "diffuse"]
     uend = diff[-1]
     assert uend["event"] == "end" and uend["converged"] == 1 and uend["sweeps"] == stu["sweeps"]
-    usync = [r for r in diff if r["event"] == "sync" and r["ctx"] == uend["ctx"]]
+    usync = [r for r in diff if r["event"] == "sync"]
     assert len(usync) == stu["sweeps"]
     assert all(r["sweeps"] == t + 1 for t, r in enumerate(usync))
 
