@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
 
     // 1. stage the range; every loop keeps SU independent loads in flight per thread
     // (out-of-range slots load a valid clamped address and store nothing)
-    constexpr int SU = 8;
+    constexpr int SU = 4;  // 4-deep batches: 62 VGPRs (8-deep ones took 111 and ran 1.3% slower)
     for (int i0 = threadIdx.x; i0 < cnt; i0 += nthr * SU) {
         T fv[SU];
         unsigned dv[SU];
@@ -553,7 +553,7 @@ __global__ void __launch_bounds__(1024) k_bld2_sweep(Bld2Args a) {
     u64 delivered = 0;
     const bool dense = ctl->dense != 0;
     {
-        constexpr int REM_U = 8;
+        constexpr int REM_U = 4;
         const i64 p0 = a.rem_base[r], p1 = a.rem_base[r + 1];
         for (i64 pb = p0 + threadIdx.x; pb < p1; pb += (i64)nthr * REM_U) {
             int src[REM_U];
