@@ -313,7 +313,9 @@ def main():
         leg = {"ms": round(d2["ms"], 3), "sweeps": d2["sweeps"], "edge_updates": d2["edges"],
                "geups": round(d2["geups"], 3), "bound": d2["bound"],
                "l1_diff_to_headline_di": float(np.abs(x2 - xd).sum()),
-               "roofline": sweep_roofline(d2, "k_bld2_sweep<%s>" % ("double" if fp32 else "float"))}
+               "roofline": sweep_roofline(d2, "k_bld2_sweep<%s>" % ("double" if fp32 else "float"),
+                                          measured_traffic("f64" if fp32 else "f32", theta_used, args.range_cut,
+                                                           used_rounds))}
         result["di_%s_fluid" % ("f64" if fp32 else "f32")] = leg
         if p2 is not None:
             l1 = float(np.abs(xd - p2.pop("x")).sum())
